@@ -1,0 +1,206 @@
+"""Semi-discrete residual dq/dt of the entropy-stable SBP-SAT discretization (ES-C) of the
+compressible Navier-Stokes equations on conforming curvilinear hexahedra.
+
+Follows eq. discEL (inviscid flux differencing), eq. NSL with eq. MacroForm (viscous
+operator in entropy variables, LDG/BR1 gradient, interior penalty), the Chandrashekar
+two-point flux, and SATs for conforming periodic interfaces. Readings of passages that
+are garbled or that defer to other papers:
+
+* volume term: sum_l sum_j D_l(i,j) (A_l,i + A_l,j) . F#(q_i, q_j), with no factor 1/2 and
+  the metric [A_lm] in both terms (the only reading consistent with the linear split
+  form, eq. convectionsplitdisc);
+* inviscid interface SAT at a node i on face (l, s) of an element, partner node nu on the
+  neighbour, n = (A_l,i + A_l,nu)/2, w_end the end weight of the 1-D norm:
+      -(s / w_end) [ F#(q_i, q_nu) . n - F(q_i) . A_l,i ]
+  plus local Lax-Friedrichs dissipation -(lam / (2 w_end)) (q_i - q_nu),
+  lam = max over the two sides of |U . n| + c |n|;
+* viscous operator with theta_a = D_a w + (s/(2 w_end)) (w_nu - w_i) on faces of direction a,
+  g_j = sum_a A_aj theta_a / J, F^V_m = sum_j C_mj g_j, fhat_l = sum_m A_lm F^V_m, and
+      sum_l D_l fhat_l + (s/(2 w_end)) (fhat_l,nu - fhat_l,i)
+      - (eta / w_end) (Chat_ll,i + Chat_ll,nu)/2 (w_i - w_nu),
+  Chat_ll = sum_{m,j} A_lm C_mj A_lj / J (eq. Chatij with the summation index fixed);
+* the output is dq/dt: the sum of the terms divided by J.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gas as G
+from .geometry import apply_D
+
+
+class Params:
+    """Problem constants: the gas, interior-penalty coefficient eta, whether interface
+    dissipation is on, and the two-point flux (0 Chandrashekar, 1 central, 2 Kennedy-Gruber)."""
+
+    def __init__(self, gamma=1.4, R=1.0, mu=0.0, Pr=0.72, eta=1.0, iface_diss=1, two_point=0):
+        self.gas = G.Gas(gamma, R, mu, Pr)
+        self.eta = eta
+        self.iface_diss = iface_diss
+        self.two_point = two_point
+
+    @classmethod
+    def of(cls, prob):
+        return cls(prob.gamma, prob.R, prob.mu, prob.Pr, prob.eta, prob.iface_diss, prob.two_point)
+
+
+def _take(u, idx, l):
+    """Slice of element arrays at index idx along direction xi_l (the axis is removed)."""
+    return np.take(u, idx, axis=u.ndim - 1 - l)
+
+
+def _index(ndim, idx, l):
+    sl = [slice(None)] * ndim
+    sl[ndim - 1 - l] = idx
+    return tuple(sl)
+
+
+def _faces(p):
+    """(l, s, face id, own index, neighbour index) for the six faces of an element."""
+    out = []
+    for l in range(3):
+        for side, s in ((0, -1.0), (1, 1.0)):
+            own = 0 if s < 0 else p
+            out.append((l, s, 2 * l + side, own, p - own))
+    return out
+
+
+def volume_term(q, metric, sbp, prm: Params):
+    """sum_l sum_j D(i_l, j_l) (A_l,i + A_l,j) . F#(q_i, q_j) over the nodes j on the xi_l line
+    through i (eq. discEL), for element arrays q (5, n, N, N, N)."""
+    flux = G.TWO_POINT[prm.two_point]
+    V = np.zeros_like(q)
+    N = sbp.N
+    for l in range(3):
+        Al = metric[3 * l:3 * l + 3]
+        for a in range(N):
+            qa, Aa = _take(q, a, l), _take(Al, a, l)
+            acc = np.zeros_like(qa)
+            for b in range(N):
+                if sbp.D[a, b] == 0.0:
+                    continue
+                qb, Ab = _take(q, b, l), _take(Al, b, l)
+                acc = acc + sbp.D[a, b] * G.contract(flux(qa, qb, prm.gas), Aa + Ab)
+            V[_index(V.ndim, a, l)] += acc
+    return V
+
+
+def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params):
+    """Interface SAT and local Lax-Friedrichs dissipation for the elements ``elems``."""
+    flux = G.TWO_POINT[prm.two_point]
+    gas = prm.gas
+    q = q_all[:, elems]
+    out = np.zeros_like(q)
+    w_end = sbp.w[0]
+    for l, s, f, own, nb in _faces(sbp.p):
+        qi = _take(q, own, l)
+        qn = _take(q_all[:, nbr[elems, f]], nb, l)
+        Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
+        An = _take(metric_all[3 * l:3 * l + 3, nbr[elems, f]], nb, l)
+        nbar = 0.5 * (Ai + An)
+        sat = -(s / w_end) * (G.contract(flux(qi, qn, gas), nbar) - G.contract(G.euler_flux(qi, gas), Ai))
+        if prm.iface_diss:
+            nn = np.sqrt((nbar * nbar).sum(0))
+
+            def speed(qx):
+                rho, u, P, T = G.primitives(qx, gas)
+                un = (u * nbar).sum(0)
+                aun = np.where(np.real(un) >= 0, un, -un)
+                return aun + G.sound_speed(qx, gas) * nn
+
+            li, ln = speed(qi), speed(qn)
+            lam = np.where(np.real(li) >= np.real(ln), li, ln)
+            sat = sat - (lam / (2.0 * w_end)) * (qi - qn)
+        out[_index(out.ndim, own, l)] += sat
+    return out
+
+
+def gradient_theta(q_all, nbr, elems, sbp, prm: Params):
+    """theta_a = D_a w + SAT^theta for the elements ``elems``, shape (3, 5, n, N, N, N)."""
+    gas = prm.gas
+    w = G.entropy_variables(q_all[:, elems], gas)
+    th = np.stack([apply_D(sbp.D, w, a) for a in range(3)])
+    w_end = sbp.w[0]
+    for a, s, f, own, nb in _faces(sbp.p):
+        wi = _take(w, own, a)
+        wn = _take(G.entropy_variables(q_all[:, nbr[elems, f]], gas), nb, a)
+        th[a][_index(w.ndim, own, a)] += (s / (2.0 * w_end)) * (wn - wi)
+    return th
+
+
+def contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params):
+    """fhat_l = sum_m A_lm F^V_m with F^V_m = sum_j C_mj g_j and g_j = sum_a A_aj theta_a / J;
+    shape (3, 5, n, N, N, N)."""
+    th = gradient_theta(q_all, nbr, elems, sbp, prm)
+    A = metric_all[:, elems]
+    J = jac_all[elems]
+    g = np.stack([sum(A[3 * a + j] * th[a] for a in range(3)) / J for j in range(3)])
+    FV = G.viscous_flux(q_all[:, elems], g, prm.gas)
+    return np.stack([sum(A[3 * l + m] * FV[m] for m in range(3)) for l in range(3)])
+
+
+def chat_ll(q, A_l, J, gas):
+    """Chat_ll = sum_{m,j} A_lm C_mj A_lj / J as 5x5 blocks, shape (5, 5, ...)."""
+    C = G.viscous_blocks(q, gas)
+    return sum(A_l[m] * C[m, j] * A_l[j] for m in range(3) for j in range(3)) / J
+
+
+def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params):
+    """sum_l D_l fhat_l + SAT^V + IP for the elements ``elems`` (eq. NSL, eq. MacroForm)."""
+    gas = prm.gas
+    elems = np.asarray(elems)
+    ring = np.unique(np.concatenate([elems, nbr[elems].ravel()]))
+    pos = {int(e): i for i, e in enumerate(ring)}
+    fh_ring = contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, ring, sbp, prm)
+    own_pos = np.array([pos[int(e)] for e in elems])
+    fh = fh_ring[:, :, own_pos]
+    out = sum(apply_D(sbp.D, fh[l], l) for l in range(3))
+    w_end = sbp.w[0]
+    q = q_all[:, elems]
+    w = G.entropy_variables(q, gas)
+    for l, s, f, own, nb in _faces(sbp.p):
+        nb_e = nbr[elems, f]
+        nb_pos = np.array([pos[int(e)] for e in nb_e])
+        fi = _take(fh[l], own, l)
+        fn = _take(fh_ring[l][:, nb_pos], nb, l)
+        sat_v = (s / (2.0 * w_end)) * (fn - fi)
+        # interior penalty
+        qi, qn = _take(q, own, l), _take(q_all[:, nb_e], nb, l)
+        wi, wn = _take(w, own, l), G.entropy_variables(qn, gas)
+        Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
+        An = _take(metric_all[3 * l:3 * l + 3, nb_e], nb, l)
+        Ji, Jn = _take(jac_all[elems], own, l), _take(jac_all[nb_e], nb, l)
+        Lm = 0.5 * (chat_ll(qi, Ai, Ji, gas) + chat_ll(qn, An, Jn, gas))
+        ip = -(prm.eta / w_end) * np.einsum("ab...,b...->a...", Lm, wi - wn)
+        out[_index(out.ndim, own, l)] += sat_v + ip
+    return out
+
+
+def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chunk=None):
+    """dq/dt for the elements ``elems`` (all by default), shape (5, n, N, N, N).
+
+    ``chunk`` splits the element list into groups evaluated one after another (memory only).
+    """
+    K = q_all.shape[1]
+    if elems is None:
+        elems = np.arange(K)
+    elems = np.asarray(elems)
+    if chunk is not None and len(elems) > chunk:
+        return np.concatenate([residual(q_all, metric_all, jac_all, nbr, sbp, prm,
+                                        elems[i:i + chunk]) for i in range(0, len(elems), chunk)],
+                              axis=1)
+    q = q_all[:, elems]
+    rhs = -volume_term(q, metric_all[:, elems], sbp, prm)
+    rhs = rhs + inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm)
+    if prm.gas.mu != 0.0:
+        rhs = rhs + viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm)
+    return rhs / jac_all[elems]
+
+
+def rk4_step(f, q, dt):
+    """Classical fourth-order Runge-Kutta step with fixed dt for dq/dt = f(q)."""
+    k1 = f(q)
+    k2 = f(q + 0.5 * dt * k1)
+    k3 = f(q + 0.5 * dt * k2)
+    k4 = f(q + dt * k3)
+    return q + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
