@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Benchmark of the ES-C SBP-SAT residual path on one MI355X.
+
+A step is one pass of the hot path over the Taylor-Green workload (compressible Navier-Stokes,
+p = 4, 32^3 warped hexahedra, FP64): one residual evaluation plus one classical RK4 step (four
+more residual evaluations and the stage updates).  The metric is node-residual evaluations per
+second (one node's 5-component dq/dt, evaluated once), in millions.
+
+Prints one JSON line.  The CPU baseline is the plain NumPy oracle, single-threaded, timed on a
+bounded sample of elements of the same workload in a child process.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mdof-residual evals/s FP64 (plain vs batched vs VJP) at <=1e-12 rel err; % FP64 peak"
+UNIT = "Mdof-residual evals/s"
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP64 FMA lanes/clk x 2 flop x 2.4 GHz
+
+
+# ------------------------------------------------------------------------------------------
+# Algorithmic work of the main residual kernel (per launch), from the per-unit figures derived
+# for the method: a pair is one unordered node pair on a line (3 N^2 lines x N(N-1)/2 pairs per
+# element), a face side is one (node, face) incidence (6 N^2 per element).
+# ------------------------------------------------------------------------------------------
+FLOP_PAIR = 70          # two-point flux contracted with A_i + A_j, applied to both nodes
+FLOP_FACE_INV = 95      # EC interface flux + Lax-Friedrichs dissipation, one side
+FLOP_NODE_INV = 30      # primitives, logarithms, final 1/J scaling
+FLOP_FACE_VISC = 330    # SAT^theta, own SAT^V, interior penalty (two viscous-flux evaluations)
+BYTES_NODE = 160        # q 40 + metric 72 + J 8 read, dq/dt 40 written
+
+
+def flop_visc_node(N):
+    # theta (3 directions x 4 comps x N FMA), g (12 x 3 FMA + scale), viscous flux and three
+    # contractions (~145), divergence (3 x 4 x N FMA)
+    return 24 * N + 75 + 145 + 24 * N
+
+
+def algorithmic_flops(p, K, viscous):
+    N = p + 1
+    pairs = K * 3 * N * N * N * (N - 1) // 2
+    faces = K * 6 * N * N
+    nodes = K * N ** 3
+    f = pairs * FLOP_PAIR + faces * FLOP_FACE_INV + nodes * FLOP_NODE_INV
+    if viscous:
+        f += nodes * flop_visc_node(N) + faces * FLOP_FACE_VISC
+    return f
+
+
+def algorithmic_bytes(p, K, viscous):
+    N = p + 1
+    b = K * N ** 3 * BYTES_NODE
+    if viscous:
+        b += K * 6 * N * N * 4 * 8   # face traces of the contravariant viscous flux (written)
+    return b
+
+
+# ------------------------------------------------------------------------------------------
+def cpu_leg(workload: str, n_sample: int, seed: int = 11):
+    """Oracle timing on a bounded element sample (run in a child with one thread)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import geometry, operators, residual as R
+
+    prob = W.config(workload)
+    sbp = operators.SBP1D(prob.p)
+    x = W.coords(prob, sbp.x).numpy()
+    q = W.state(prob, torch.as_tensor(x)).numpy()
+    nbr = W.neighbours(prob.E)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S = np.sort(rng.choice(prob.K, size=n_sample, replace=False))
+    ring = np.unique(np.concatenate([S, nbr[S].ravel(), nbr[nbr[S].ravel()].ravel()]))
+    metric = np.zeros((9,) + x.shape[1:])
+    jac = np.ones(x.shape[1:])
+    metric[:, ring] = geometry.curl_metrics(x[:, ring], sbp.D)
+    jac[ring] = geometry.jacobian(x[:, ring], sbp.D)
+    prm = R.Params.of(prob)
+    t0 = time.perf_counter()
+    R.residual(q, metric, jac, nbr, sbp, prm, elems=S, chunk=1024)
+    t = time.perf_counter() - t0
+    nodes = n_sample * prob.N ** 3
+    print(json.dumps({"value": nodes / t / 1e6, "seconds": t, "nodes": nodes, "elems": int(n_sample)}))
+
+
+def run_cpu_baseline(workload: str, n_sample: int):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    env["CUDA_VISIBLE_DEVICES"] = ""
+    env["HIP_VISIBLE_DEVICES"] = ""
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", workload,
+           "--cpu-sample", str(n_sample)]
+    res = subprocess.run(cmd, capture_output=True, text=True, env=env, cwd=ROOT)
+    if res.returncode != 0:
+        sys.stderr.write(res.stderr)
+        return None
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+# ------------------------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ns_tgv_p4_e32")
+    ap.add_argument("--cpu-sample", type=int, default=12288, help="elements in the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    args = ap.parse_args()
+
+    if args.cpu_leg:
+        cpu_leg(args.workload, args.cpu_sample)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by element blocks across GPUs, which this build does not run)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1911_10966_amd as P
+    import workloads as W
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    prob = W.config(args.workload)
+    N = prob.p + 1
+    x1d, _, _ = P.lgl_operator(prob.p)
+    coords = W.coords(prob, x1d, device=dev)
+    metric, jac = P.metrics(prob.p, coords.reshape(3, -1).contiguous())
+    q = W.state(prob, coords).reshape(-1).contiguous()
+    dt = torch.tensor([W.cfl_dt(prob, coords)], dtype=torch.float64, device=dev)
+    del coords
+    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(W.neighbours(prob.E), device=dev),
+                   metric=metric, jac=jac, gamma=prob.gamma, R=prob.R, mu=prob.mu, Pr=prob.Pr,
+                   eta=prob.eta, iface_diss=prob.iface_diss, two_point=prob.two_point)
+    ps = P.ProblemSet([dp])
+    out = torch.empty_like(q)
+
+    def step():
+        ps.residual(q, out)
+        ps.rk_step(q, dt, 1)
+
+    for _ in range(args.warmup):
+        step()
+    ps.status()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ps.status()
+    ms_step = ms_total / args.steps
+    res_per_step = 5
+    node_res = res_per_step * prob.n_nodes
+    value = node_res * args.steps / (ms_total * 1e-3) / 1e6
+
+    # dominant kernel: the fused residual kernel, timed with events on the launch stream
+    kms = [ps.profile_residual(q, out) for _ in range(args.kernel_reps)]
+    kmean = sum(kms) / len(kms)
+    visc = prob.mu > 0
+    flops = algorithmic_flops(prob.p, prob.K, visc)
+    nbytes = algorithmic_bytes(prob.p, prob.K, visc)
+    alu = flops / (kmean * 1e-3) / 1e12
+    hbm = nbytes / (kmean * 1e-3) / 1e9
+    if alu / FP64_VALU_PEAK_TFLOPS >= hbm / HBM_PEAK_GBS:
+        roof = {"bound": "alu", "achieved": round(alu, 3), "peak": FP64_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu / FP64_VALU_PEAK_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm / HBM_PEAK_GBS, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = "k_residual"
+    roof["kernel_ms"] = round(kmean, 4)
+    roof["hbm_GBps_algorithmic"] = round(hbm, 1)
+    roof["fp64_TFLOPs_algorithmic"] = round(alu, 3)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        r = run_cpu_baseline(args.workload, args.cpu_sample)
+        if r is not None:
+            cpu = {"value": round(r["value"], 4), "unit": UNIT, "cores": 1, "kind": "oracle",
+                   "sample": f"one residual of {r['elems']} randomly chosen elements "
+                             f"({r['nodes']} nodes) of {args.workload}, {r['seconds']:.1f} s"}
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "p": prob.p, "elements": prob.K,
+                   "nodes": prob.n_nodes, "step": "1 residual + 1 RK4 step (5 residual evaluations)",
+                   "Re": prob.Re, "Ma": prob.Ma, "parallelism": "none (1 GPU)"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,129 @@
+/*
+ * sbp.h -- C ABI of the MI355X (gfx950) library that evaluates the semi-discrete residual of the
+ * entropy-stable SBP-SAT discontinuous collocation discretization (ES-C) of the compressible
+ * Navier-Stokes equations on conforming curvilinear hexahedra, as defined in Rojas, Boukharfane,
+ * Dalcin, Del Rey Fernandez, Ranocha, Keyes and Parsani, "On the robustness and performance of
+ * entropy stable discontinuous collocation methods for the compressible Navier-Stokes equations"
+ * (arXiv 1911.10966), section "Discretization of the compressible Navier-Stokes equations".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - N = p + 1 Legendre-Gauss-Lobatto nodes per direction (Notation section, Definition "SBP").
+ * - Element e has N^3 nodes numbered i1 + N*i2 + N*N*i3 (xi_1 fastest).  Node-wise arrays are
+ *   structure-of-arrays: component c of node n of a problem with K elements sits at [c*K*N^3 + e*N^3 + n].
+ * - State q = [rho, rho U_1, rho U_2, rho U_3, rho E] (eq. compressible_ns), 5 components.
+ * - metric: 9 components, entry 3*l + m is J dxi_l/dx_m (0-based l, m) at the node; jac: J > 0.
+ *   These are the diagonal matrices [A_lm] and J_kappa of the linear convection-diffusion section.
+ *   The residual is entropy conservative only when the metrics satisfy the discrete geometric
+ *   conservation law (eq. discGCLconvection); sbp_metrics() produces such metrics (curl form).
+ * - nbr: [K][6] int32, face f = 2*l + s (s = 0 for the xi_l = -1 face, 1 for xi_l = +1) of element e
+ *   touches element nbr[e*6 + f]; faces are conforming and aligned (the neighbour's opposite face,
+ *   same tangential node indices).  Periodic grids list wrap-around neighbours.
+ * - Pointers marked "device" are HIP device allocations owned by the caller; the library never
+ *   frees them and keeps no reference after the call returns (stream-ordered work may still read
+ *   them until the stream reaches that point).  All device arrays must be 8-byte aligned.
+ * - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued asynchronously; argument
+ *   and launch errors are returned immediately.  Non-physical states (rho <= 0, P <= 0 or a
+ *   non-finite value) raise a sticky device flag that sbp_status() reports.
+ * - Return codes: SBP_OK or a negative SBP_ERR_* code; sbp_error_string() describes it.
+ */
+#ifndef SBP_H
+#define SBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBP_OK 0
+#define SBP_ERR_ARG (-1)         /* null/misaligned pointer, bad size, bad option value       */
+#define SBP_ERR_DEGREE (-2)      /* p outside [1, SBP_MAX_P]                                   */
+#define SBP_ERR_MESH (-3)        /* neighbour index outside [0, K)                             */
+#define SBP_ERR_NONPHYSICAL (-4) /* reported by sbp_status: rho <= 0, P <= 0 or non-finite    */
+#define SBP_ERR_HIP (-5)         /* a HIP runtime call failed                                  */
+#define SBP_ERR_WORKSPACE (-6)   /* workspace missing or smaller than sbp_workspace_bytes()    */
+
+#define SBP_MAX_P 8
+
+#define SBP_FLUX_CHANDRASHEKAR 0 /* entropy-conservative two-point flux (ES-C)                 */
+#define SBP_FLUX_CENTRAL 1       /* arithmetic mean of the nodal fluxes                        */
+#define SBP_FLUX_KENNEDY_GRUBER 2 /* split form SF-KG                                          */
+
+/* One periodic problem.  Constants follow the constituent relations of the compressible
+ * Navier-Stokes section: P = rho R T, c_p = gamma R / (gamma - 1), constant viscosity mu and
+ * conductivity kappa = mu c_p / Pr; mu == 0 evaluates the Euler residual only. */
+typedef struct sbp_problem {
+    int32_t p;              /* polynomial degree, 1..SBP_MAX_P                                 */
+    int32_t iface_diss;     /* 1: local Lax-Friedrichs interface dissipation (entropy stable)  */
+    int64_t n_elem;         /* K > 0                                                           */
+    const int32_t *nbr;     /* device [K][6]                                                   */
+    const double *metric;   /* device SoA [9][K*N^3]                                           */
+    const double *jac;      /* device [K*N^3]                                                  */
+    double gamma, R, mu, Pr;
+    double eta;             /* interior-penalty coefficient >= 0                               */
+    int32_t two_point;      /* SBP_FLUX_*                                                      */
+    int32_t reserved;       /* must be 0                                                       */
+} sbp_problem;
+
+/* Library version, for diagnostics. */
+int sbp_version(void);
+
+/* Human-readable text for a return code (static storage). */
+const char *sbp_error_string(int code);
+
+/* The 1-D degree-p LGL SBP operator (Notation section, Definition "SBP"): nodes x[N] in [-1, 1],
+ * quadrature weights w[N] (the diagonal norm P) and the collocation derivative D[N*N] (row-major,
+ * D = P^{-1} Q, exact for polynomials of degree <= p).  Host pointers owned by the caller.
+ * Any of x, w, D may be NULL.  Returns SBP_ERR_DEGREE for p outside [1, 15]. */
+int sbp_lgl_operator(int32_t p, double *x, double *w, double *D);
+
+/* Curl-form metric terms J dxi_l/dx_m and Jacobian J from nodal coordinates (linear
+ * convection-diffusion section: metric terms [A_lm] satisfying eq. discGCLconvection).
+ * coords: device SoA [3][K*N^3] physical coordinates; metric: device [9][K*N^3] out; jac: device
+ * [K*N^3] out.  The derivatives are the degree-p collocation derivative along each direction. */
+int sbp_metrics(int32_t p, int64_t n_elem, const double *coords, double *metric, double *jac,
+                void *stream);
+
+/* Device workspace (bytes) needed by sbp_residual, sbp_rk_step and sbp_residual_vjp for this
+ * problem set.  0 on invalid arguments. */
+size_t sbp_workspace_bytes(const sbp_problem *probs, int32_t n_prob);
+
+/* Semi-discrete residual dq/dt (eqs. discEL and NSL, divided by J): Hadamard flux differencing with
+ * the two-point flux and averaged metrics, interface SATs (entropy-conservative flux plus optional
+ * Lax-Friedrichs dissipation) and, for mu > 0, the BR1/interior-penalty viscous operator in entropy
+ * variables.  probs: host array of n_prob >= 1 problems; q, dqdt: device arrays holding the problems'
+ * SoA blocks back to back (problem b at offset 5 * sum_{b'<b} K_b' N_b'^3).  ws: device workspace of
+ * ws_bytes >= sbp_workspace_bytes(probs, n_prob), owned by the caller; calls sharing a workspace
+ * must be serialized on one stream.  dqdt must not alias q. */
+int sbp_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Classical fourth-order Runge-Kutta steps with fixed time steps: q <- RK4(q, dt[b]) n_steps times.
+ * q: device in/out, same layout as sbp_residual; dt: device [n_prob].  The four stages of a step are
+ * recorded once into a HIP graph per (problem set, q, dt, workspace) and replayed. */
+int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const double *dt,
+                int32_t n_steps, void *ws, size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product qbar = (d(dq/dt)/dq)^T gbar of the residual of sbp_residual, with each
+ * element recomputing its forward intermediates.  q, gbar, qbar: device, same layout as q. */
+int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
+                     double *qbar, void *ws, size_t ws_bytes, void *stream);
+
+/* Profiling variant of sbp_residual for one problem (n_prob == 1): the same launches, with HIP
+ * events recorded on `stream` around the main residual kernel; waits for the end event and stores
+ * that kernel's duration in *kernel_ms (host pointer).  Not for use under graph capture. */
+int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
+                         void *ws, size_t ws_bytes, void *stream, float *kernel_ms);
+
+/* Waits for `stream`, then reports and clears the workspace's sticky device flags:
+ * *flags = 0 when every state seen since the last call was physical, else SBP_ERR_NONPHYSICAL's
+ * bit 1.  Returns SBP_ERR_NONPHYSICAL in that case, SBP_OK otherwise. */
+int sbp_status(void *ws, void *stream, int32_t *flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBP_H */

@@ -25,7 +25,8 @@ def legendre(p: int, x):
     for n in range(1, p):
         p0, p1 = p1, ((2 * n + 1) * x * p1 - n * p0) / (n + 1)
     # derivative from (x^2 - 1) P_p' = p (x P_p - P_{p-1}), valid for |x| < 1
-    dp = p * (x * p1 - p0) / (x * x - 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dp = p * (x * p1 - p0) / (x * x - 1)
     return p1, dp
 
 

@@ -1,0 +1,171 @@
+"""Python entry points over the C ABI.  Every step of the residual runs in the HIP library; torch
+provides device memory and the current stream only."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+F64 = torch.float64
+
+
+def lgl_operator(p: int):
+    """(x, w, D) of the degree-p LGL SBP operator, computed by the library (host)."""
+    N = p + 1
+    x = np.zeros(N)
+    w = np.zeros(N)
+    D = np.zeros(N * N)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().sbp_lgl_operator(p, x.ctypes.data_as(dp), w.ctypes.data_as(dp), D.ctypes.data_as(dp)),
+          "sbp_lgl_operator")
+    return x, w, D.reshape(N, N)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def metrics(p: int, coords: torch.Tensor):
+    """Curl-form metric terms (9, nodes) and Jacobian (nodes,) from device coordinates (3, nodes)."""
+    _need(coords, F64, "coords")
+    nodes = coords.numel() // 3
+    N3 = (p + 1) ** 3
+    K = nodes // N3
+    metric = torch.empty((9, nodes), dtype=F64, device=coords.device)
+    jac = torch.empty((nodes,), dtype=F64, device=coords.device)
+    check(lib().sbp_metrics(p, K, _ptr(coords), _ptr(metric), _ptr(jac), _stream()), "sbp_metrics")
+    return metric, jac
+
+
+@dataclass
+class Problem:
+    """One periodic problem on the device: degree, element count, neighbour table, metrics, constants."""
+
+    p: int
+    n_elem: int
+    nbr: torch.Tensor       # int32 (K, 6)
+    metric: torch.Tensor    # float64 (9, nodes)
+    jac: torch.Tensor       # float64 (nodes,)
+    gamma: float = 1.4
+    R: float = 1.0
+    mu: float = 0.0
+    Pr: float = 0.72
+    eta: float = 1.0
+    iface_diss: int = 1
+    two_point: int = 0
+
+    @property
+    def nodes(self) -> int:
+        return self.n_elem * (self.p + 1) ** 3
+
+    def c_struct(self) -> _lib.sbp_problem:
+        _need(self.nbr, torch.int32, "nbr")
+        _need(self.metric, F64, "metric")
+        _need(self.jac, F64, "jac")
+        return _lib.sbp_problem(self.p, self.iface_diss, self.n_elem, self.nbr.data_ptr(),
+                                self.metric.data_ptr(), self.jac.data_ptr(), self.gamma, self.R,
+                                self.mu, self.Pr, self.eta, self.two_point, 0)
+
+
+class ProblemSet:
+    """Problems evaluated together (n = 1: plain path; n > 1: batched path) with their workspace."""
+
+    def __init__(self, problems: Sequence[Problem]):
+        self.problems: List[Problem] = list(problems)
+        n = len(self.problems)
+        self._arr = (_lib.sbp_problem * n)(*[p.c_struct() for p in self.problems])
+        self.n = n
+        self.ws_bytes = int(lib().sbp_workspace_bytes(self._arr, n))
+        if self.ws_bytes == 0:
+            raise _lib.SBPError(_lib.SBP_ERR_ARG, "sbp_workspace_bytes")
+        dev = self.problems[0].metric.device
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.total_nodes = sum(p.nodes for p in self.problems)
+
+    def state_numel(self) -> int:
+        return 5 * self.total_nodes
+
+    def _check_state(self, t, name):
+        _need(t, F64, name)
+        if t.numel() != self.state_numel():
+            raise ValueError(f"{name} has {t.numel()} entries, expected {self.state_numel()}")
+
+    def residual(self, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_state(q, "q")
+        if out is None:
+            out = torch.empty_like(q)
+        self._check_state(out, "out")
+        check(lib().sbp_residual(self._arr, self.n, _ptr(q), _ptr(out), _ptr(self.ws), self.ws_bytes,
+                                 _stream()), "sbp_residual")
+        return out
+
+    def profile_residual(self, q: torch.Tensor, out: torch.Tensor) -> float:
+        """Runs the residual once and returns the main kernel's duration in ms (HIP events)."""
+        self._check_state(q, "q")
+        self._check_state(out, "out")
+        ms = ctypes.c_float(0.0)
+        check(lib().sbp_profile_residual(self._arr, self.n, _ptr(q), _ptr(out), _ptr(self.ws),
+                                         self.ws_bytes, _stream(), ctypes.byref(ms)),
+              "sbp_profile_residual")
+        return float(ms.value)
+
+    def rk_step(self, q: torch.Tensor, dt: torch.Tensor, n_steps: int = 1) -> torch.Tensor:
+        """In-place classical RK4 steps; dt is a device float64 tensor with one entry per problem."""
+        self._check_state(q, "q")
+        _need(dt, F64, "dt")
+        if dt.numel() != self.n:
+            raise ValueError("dt needs one entry per problem")
+        check(lib().sbp_rk_step(self._arr, self.n, _ptr(q), _ptr(dt), n_steps, _ptr(self.ws),
+                                self.ws_bytes, _stream()), "sbp_rk_step")
+        return q
+
+    def residual_vjp(self, q: torch.Tensor, gbar: torch.Tensor, out: Optional[torch.Tensor] = None):
+        self._check_state(q, "q")
+        self._check_state(gbar, "gbar")
+        if out is None:
+            out = torch.empty_like(q)
+        self._check_state(out, "out")
+        check(lib().sbp_residual_vjp(self._arr, self.n, _ptr(q), _ptr(gbar), _ptr(out), _ptr(self.ws),
+                                     self.ws_bytes, _stream()), "sbp_residual_vjp")
+        return out
+
+    def status(self) -> int:
+        """Waits for the stream; raises SBPError if a non-physical state or bad neighbour was seen."""
+        flags = ctypes.c_int32(0)
+        rc = lib().sbp_status(_ptr(self.ws), _stream(), ctypes.byref(flags))
+        check(rc, "sbp_status")
+        return flags.value
+
+
+class SBPResidual(torch.autograd.Function):
+    """dq/dt = residual(q) with the hand-written vector-Jacobian product as its backward."""
+
+    @staticmethod
+    def forward(ctx, q, pset: ProblemSet):
+        ctx.pset = pset
+        ctx.save_for_backward(q)
+        return pset.residual(q.contiguous())
+
+    @staticmethod
+    def backward(ctx, gbar):
+        (q,) = ctx.saved_tensors
+        return ctx.pset.residual_vjp(q.contiguous(), gbar.contiguous()), None

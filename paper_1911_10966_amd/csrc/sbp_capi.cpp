@@ -1,0 +1,406 @@
+// C ABI of the ES-C SBP-SAT residual library (declared in include/sbp.h): argument checking,
+// the 1-D LGL operator, workspace layout, launch sequencing and the RK4 graph cache.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sbp.h"
+#include "sbp_internal.h"
+
+namespace {
+
+constexpr int kMaxOpP = 15;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------------------------------------
+// 1-D LGL operator.  Interior nodes are the roots of P_p' found by Newton's method in long
+// double; the derivative matrix is built from barycentric weights (D_ij = (l_j/l_i)/(x_i-x_j),
+// D_ii = -sum_{j != i} D_ij) and the weights from w_i = 2 / (p (p+1) P_p(x_i)^2).
+// ------------------------------------------------------------------------------------------
+void legendre_ld(int p, long double x, long double &P, long double &dP) {
+    long double p0 = 1.0L, p1 = x, d0 = 0.0L, d1 = 1.0L;
+    if (p == 0) { P = 1.0L; dP = 0.0L; return; }
+    for (int n = 1; n < p; ++n) {
+        const long double p2 = ((2 * n + 1) * x * p1 - n * p0) / (n + 1);
+        const long double d2 = d0 + (2 * n + 1) * p1;  // P'_{n+1} = P'_{n-1} + (2n+1) P_n
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    P = p1;
+    dP = d1;
+}
+
+void lgl_ld(int p, std::vector<long double> &x, std::vector<long double> &w,
+            std::vector<long double> &D) {
+    const int N = p + 1;
+    x.assign(N, 0.0L);
+    w.assign(N, 0.0L);
+    D.assign(N * N, 0.0L);
+    const long double pi = 3.14159265358979323846264338327950288L;
+    x[0] = -1.0L;
+    x[p] = 1.0L;
+    for (int i = 1; i < p; ++i) {
+        long double xi = -std::cos(pi * i / p);
+        for (int it = 0; it < 100; ++it) {
+            long double P, dP;
+            legendre_ld(p, xi, P, dP);
+            const long double d2P = (2.0L * xi * dP - p * (p + 1.0L) * P) / (1.0L - xi * xi);
+            const long double step = dP / d2P;
+            xi -= step;
+            if (std::fabs(step) < 1e-30L) break;
+        }
+        x[i] = xi;
+    }
+    for (int i = 0; i < N; ++i) {
+        long double P, dP;
+        legendre_ld(p, x[i], P, dP);
+        w[i] = 2.0L / (p * (p + 1.0L) * P * P);
+    }
+    std::vector<long double> lam(N, 1.0L);
+    for (int j = 0; j < N; ++j) {
+        long double prod = 1.0L;
+        for (int k = 0; k < N; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        lam[j] = 1.0L / prod;
+    }
+    for (int i = 0; i < N; ++i) {
+        long double diag = 0.0L;
+        for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            const long double v = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[i * N + j] = v;
+            diag -= v;
+        }
+        D[i * N + i] = diag;
+    }
+}
+
+struct Op {
+    double x[16], w[16], D[256];
+};
+
+const Op &host_op(int p) {
+    static Op ops[kMaxOpP + 1];
+    static bool done[kMaxOpP + 1] = {};
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!done[p]) {
+        std::vector<long double> x, w, D;
+        lgl_ld(p, x, w, D);
+        const int N = p + 1;
+        for (int i = 0; i < N; ++i) { ops[p].x[i] = (double)x[i]; ops[p].w[i] = (double)w[i]; }
+        for (int i = 0; i < N * N; ++i) ops[p].D[i] = (double)D[i];
+        done[p] = true;
+    }
+    return ops[p];
+}
+
+// Device copies of D for p = 1..kMaxOpP, one table per device.
+const double *device_D(int p) {
+    static std::mutex mu;
+    static std::map<int, double *> tables;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = tables.find(dev);
+    if (it == tables.end()) {
+        double *buf = nullptr;
+        if (hipMalloc(&buf, sizeof(double) * 256 * (kMaxOpP + 1)) != hipSuccess) return nullptr;
+        std::vector<double> host(256 * (kMaxOpP + 1), 0.0);
+        for (int pp = 1; pp <= kMaxOpP; ++pp) {
+            const Op &o = host_op(pp);
+            std::memcpy(host.data() + 256 * pp, o.D, sizeof(double) * (pp + 1) * (pp + 1));
+        }
+        if (hipMemcpy(buf, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return nullptr;
+        it = tables.emplace(dev, buf).first;
+    }
+    return it->second + 256 * p;
+}
+
+bool aligned8(const void *p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % 8) == 0; }
+
+int check_problem(const sbp_problem &pr) {
+    if (pr.p < 1 || pr.p > SBP_MAX_P) return SBP_ERR_DEGREE;
+    if (pr.n_elem <= 0) return SBP_ERR_ARG;
+    if (!aligned8(pr.metric) || !aligned8(pr.jac) || pr.nbr == nullptr ||
+        (reinterpret_cast<uintptr_t>(pr.nbr) % 4) != 0)
+        return SBP_ERR_ARG;
+    if (!(pr.gamma > 1.0) || !(pr.R > 0.0) || !(pr.mu >= 0.0) || !(pr.eta >= 0.0)) return SBP_ERR_ARG;
+    if (pr.mu > 0.0 && !(pr.Pr > 0.0)) return SBP_ERR_ARG;
+    if (pr.two_point < 0 || pr.two_point > 2 || pr.reserved != 0) return SBP_ERR_ARG;
+    if (pr.iface_diss != 0 && pr.iface_diss != 1) return SBP_ERR_ARG;
+    return SBP_OK;
+}
+
+long long nodes_of(const sbp_problem &pr) {
+    const long long N = pr.p + 1;
+    return pr.n_elem * N * N * N;
+}
+
+// Workspace layout: [flags | per-problem viscous traces | RK buffers acc, qs, k].
+struct Layout {
+    size_t flags = 0;
+    std::vector<size_t> trace;  // offset per problem (0 if inviscid)
+    size_t rk = 0;              // offset of the RK block
+    size_t total_state = 0;     // doubles in one state-sized buffer
+    size_t bytes = 0;
+};
+
+Layout layout_of(const sbp_problem *probs, int n) {
+    Layout L;
+    size_t off = align_up(sizeof(int) * 16);
+    L.trace.resize(n, 0);
+    size_t states = 0;
+    for (int b = 0; b < n; ++b) {
+        const long long N = probs[b].p + 1;
+        if (probs[b].mu > 0.0) {
+            L.trace[b] = off;
+            off += align_up(sizeof(double) * (size_t)probs[b].n_elem * 6 * 4 * N * N);
+        }
+        states += 5 * (size_t)nodes_of(probs[b]);
+    }
+    L.rk = off;
+    L.total_state = states;
+    off += 3 * align_up(sizeof(double) * states);
+    L.bytes = off;
+    return L;
+}
+
+int validate(const sbp_problem *probs, int32_t n_prob, void *ws, size_t ws_bytes, Layout &L) {
+    if (probs == nullptr || n_prob < 1) return SBP_ERR_ARG;
+    for (int b = 0; b < n_prob; ++b) {
+        const int rc = check_problem(probs[b]);
+        if (rc != SBP_OK) return rc;
+    }
+    L = layout_of(probs, n_prob);
+    if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < L.bytes)
+        return SBP_ERR_WORKSPACE;
+    return SBP_OK;
+}
+
+sbp::ResArgs res_args(const sbp_problem &pr, const double *q, double *out, char *ws, size_t trace_off) {
+    sbp::ResArgs a{};
+    const int N = pr.p + 1;
+    a.q = q;
+    a.out = out;
+    a.metric = pr.metric;
+    a.jac = pr.jac;
+    a.nbr = pr.nbr;
+    a.trace = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + trace_off) : nullptr;
+    a.status = reinterpret_cast<int *>(ws);
+    a.D = device_D(pr.p);
+    a.K = pr.n_elem;
+    a.nodes = pr.n_elem * (long long)N * N * N;
+    a.gamma = pr.gamma;
+    a.R = pr.R;
+    a.mu = pr.mu;
+    a.Pr = pr.Pr;
+    a.eta = pr.eta;
+    a.w_end = host_op(pr.p).w[0];
+    a.iface_diss = pr.iface_diss;
+    a.two_point = pr.two_point;
+    return a;
+}
+
+int residual_all(const sbp_problem *probs, int n, const double *q, double *out, char *ws,
+                 const Layout &L, hipStream_t s) {
+    size_t off = 0;
+    for (int b = 0; b < n; ++b) {
+        sbp::ResArgs a = res_args(probs[b], q + off, out + off, ws, L.trace[b]);
+        if (a.D == nullptr) return SBP_ERR_HIP;
+        if (sbp::launch_residual(probs[b].p, a, s) != 0) return SBP_ERR_HIP;
+        off += 5 * (size_t)nodes_of(probs[b]);
+    }
+    return SBP_OK;
+}
+
+// One RK4 step = four (residual, stage update) pairs.
+int rk_step_launches(const sbp_problem *probs, int n, double *q, const double *dt, char *ws,
+                     const Layout &L, hipStream_t s) {
+    double *acc = reinterpret_cast<double *>(ws + L.rk);
+    double *qs = reinterpret_cast<double *>(ws + L.rk + align_up(sizeof(double) * L.total_state));
+    double *k = reinterpret_cast<double *>(ws + L.rk + 2 * align_up(sizeof(double) * L.total_state));
+    for (int stage = 0; stage < 4; ++stage) {
+        const double *src = stage == 0 ? q : qs;
+        const int rc = residual_all(probs, n, src, k, ws, L, s);
+        if (rc != SBP_OK) return rc;
+        size_t off = 0;
+        for (int b = 0; b < n; ++b) {
+            const long long cnt = 5 * nodes_of(probs[b]);
+            sbp::RkArgs r{q + off, acc + off, qs + off, k + off, dt + b, cnt, stage};
+            if (sbp::launch_rk_stage(r, s) != 0) return SBP_ERR_HIP;
+            off += cnt;
+        }
+    }
+    return SBP_OK;
+}
+
+struct GraphKey {
+    std::string probs;
+    const void *q, *dt, *ws;
+    int dev;
+    bool operator<(const GraphKey &o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (q != o.q) return q < o.q;
+        if (dt != o.dt) return dt < o.dt;
+        if (ws != o.ws) return ws < o.ws;
+        return probs < o.probs;
+    }
+};
+
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+}  // namespace
+
+extern "C" {
+
+int sbp_version(void) { return 100; }
+
+const char *sbp_error_string(int code) {
+    switch (code) {
+        case SBP_OK: return "ok";
+        case SBP_ERR_ARG: return "invalid argument (null/misaligned pointer, size or option)";
+        case SBP_ERR_DEGREE: return "polynomial degree out of range";
+        case SBP_ERR_MESH: return "neighbour index out of range";
+        case SBP_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, P <= 0 or non-finite)";
+        case SBP_ERR_HIP: return "HIP runtime error";
+        case SBP_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        default: return "unknown error";
+    }
+}
+
+int sbp_lgl_operator(int32_t p, double *x, double *w, double *D) {
+    if (p < 1 || p > kMaxOpP) return SBP_ERR_DEGREE;
+    const Op &o = host_op(p);
+    const int N = p + 1;
+    if (x) std::memcpy(x, o.x, sizeof(double) * N);
+    if (w) std::memcpy(w, o.w, sizeof(double) * N);
+    if (D) std::memcpy(D, o.D, sizeof(double) * N * N);
+    return SBP_OK;
+}
+
+int sbp_metrics(int32_t p, int64_t n_elem, const double *coords, double *metric, double *jac,
+                void *stream) {
+    if (p < 1 || p > 9) return SBP_ERR_DEGREE;
+    if (n_elem <= 0 || !aligned8(coords) || !aligned8(metric) || !aligned8(jac)) return SBP_ERR_ARG;
+    const double *D = device_D(p);
+    if (!D) return SBP_ERR_HIP;
+    return sbp::launch_metrics(p, n_elem, coords, metric, jac, D, (hipStream_t)stream) == 0
+               ? SBP_OK : SBP_ERR_HIP;
+}
+
+size_t sbp_workspace_bytes(const sbp_problem *probs, int32_t n_prob) {
+    if (probs == nullptr || n_prob < 1) return 0;
+    for (int b = 0; b < n_prob; ++b)
+        if (check_problem(probs[b]) != SBP_OK) return 0;
+    return layout_of(probs, n_prob).bytes;
+}
+
+int sbp_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt, void *ws,
+                 size_t ws_bytes, void *stream) {
+    Layout L;
+    int rc = validate(probs, n_prob, ws, ws_bytes, L);
+    if (rc != SBP_OK) return rc;
+    if (!aligned8(q) || !aligned8(dqdt) || q == dqdt) return SBP_ERR_ARG;
+    return residual_all(probs, n_prob, q, dqdt, static_cast<char *>(ws), L, (hipStream_t)stream);
+}
+
+int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const double *dt,
+                int32_t n_steps, void *ws, size_t ws_bytes, void *stream) {
+    Layout L;
+    int rc = validate(probs, n_prob, ws, ws_bytes, L);
+    if (rc != SBP_OK) return rc;
+    if (!aligned8(q) || !aligned8(dt) || n_steps < 0) return SBP_ERR_ARG;
+    if (n_steps == 0) return SBP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SBP_ERR_HIP;
+    // make sure the operator tables exist before capture (no allocation inside a capture)
+    for (int b = 0; b < n_prob; ++b)
+        if (!device_D(probs[b].p)) return SBP_ERR_HIP;
+    GraphKey key{std::string(reinterpret_cast<const char *>(probs), sizeof(sbp_problem) * n_prob),
+                 q, dt, ws, dev};
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) exec = it->second;
+    }
+    if (exec == nullptr) {
+        hipStream_t cap;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SBP_ERR_HIP;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            hipStreamDestroy(cap);
+            return SBP_ERR_HIP;
+        }
+        rc = rk_step_launches(probs, n_prob, q, dt, static_cast<char *>(ws), L, cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        hipStreamDestroy(cap);
+        if (rc != SBP_OK || ec != hipSuccess || graph == nullptr) {
+            if (graph) hipGraphDestroy(graph);
+            return rc != SBP_OK ? rc : SBP_ERR_HIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) return SBP_ERR_HIP;
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        g_graphs[key] = exec;
+    }
+    for (int i = 0; i < n_steps; ++i)
+        if (hipGraphLaunch(exec, s) != hipSuccess) return SBP_ERR_HIP;
+    return SBP_OK;
+}
+
+int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
+                     double *qbar, void *ws, size_t ws_bytes, void *stream) {
+    (void)probs; (void)n_prob; (void)q; (void)gbar; (void)qbar; (void)ws; (void)ws_bytes; (void)stream;
+    return SBP_ERR_ARG;
+}
+
+int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
+                         void *ws, size_t ws_bytes, void *stream, float *kernel_ms) {
+    Layout L;
+    int rc = validate(probs, n_prob, ws, ws_bytes, L);
+    if (rc != SBP_OK) return rc;
+    if (n_prob != 1 || kernel_ms == nullptr || !aligned8(q) || !aligned8(dqdt) || q == dqdt)
+        return SBP_ERR_ARG;
+    sbp::KernelTimer &tm = sbp::residual_timer();
+    if (tm.begin == nullptr) {
+        if (hipEventCreate(&tm.begin) != hipSuccess || hipEventCreate(&tm.end) != hipSuccess)
+            return SBP_ERR_HIP;
+    }
+    tm.enabled = true;
+    rc = residual_all(probs, n_prob, q, dqdt, static_cast<char *>(ws), L, (hipStream_t)stream);
+    tm.enabled = false;
+    if (rc != SBP_OK) return rc;
+    if (hipEventSynchronize(tm.end) != hipSuccess) return SBP_ERR_HIP;
+    if (hipEventElapsedTime(kernel_ms, tm.begin, tm.end) != hipSuccess) return SBP_ERR_HIP;
+    return SBP_OK;
+}
+
+int sbp_status(void *ws, void *stream, int32_t *flags) {
+    if (ws == nullptr || flags == nullptr) return SBP_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamSynchronize(s) != hipSuccess) return SBP_ERR_HIP;
+    int host = 0;
+    if (hipMemcpy(&host, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SBP_ERR_HIP;
+    const int zero = 0;
+    if (hipMemcpy(ws, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SBP_ERR_HIP;
+    *flags = host;
+    if (host & sbp::FLAG_NONPHYSICAL) return SBP_ERR_NONPHYSICAL;
+    if (host & sbp::FLAG_MESH) return SBP_ERR_MESH;
+    return SBP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,689 @@
+// gfx950 kernels of the ES-C SBP-SAT residual (arXiv 1911.10966, section "Discretization of the
+// compressible Navier-Stokes equations").  FP64 throughout.
+//
+// Residual kernel layout: one workgroup holds EPW elements, one thread per node (wave64 tiles of
+// the element's N^3 nodes).  Node data needed by line partners (rho, U, beta = rho/(2P), log rho,
+// log beta, |U|^2, the metric row of the current direction) is staged in LDS.  The flux-differencing
+// sum over each line uses the symmetry of the two-point flux: in round r a node evaluates the pair
+// with the node r places further along the line (cyclically), keeps D(a,b) f and hands D(b,a) f to
+// its partner through an LDS mailbox, so every pair is evaluated once.
+#include "sbp_internal.h"
+
+#include <math.h>
+
+namespace sbp {
+namespace {
+
+constexpr int NT_OF(int nodes) { return ((nodes + 63) / 64) * 64; }
+
+// Reciprocal: hardware estimate refined by two Newton steps (a few ulp; no IEEE fixup needed
+// for the strictly positive, finite operands used here).
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// With z = (a-b)/(a+b) and u = z^2:  log(a/b) = 2 artanh z = 2 z F(u),  F(u) = sum_k u^k/(2k+1),
+// so the logarithmic mean is (a+b)/(2 F(u)) and its inverse 2 F(u)/(a+b).  For u < 1e-2 the
+// series below (F through u^7, G = 1/F through u^7) are accurate to < 1e-17 relative.
+__device__ __forceinline__ double series_F(double u) {
+    double r = 1.0 / 15.0;
+    r = fma(r, u, 1.0 / 13.0);
+    r = fma(r, u, 1.0 / 11.0);
+    r = fma(r, u, 1.0 / 9.0);
+    r = fma(r, u, 1.0 / 7.0);
+    r = fma(r, u, 1.0 / 5.0);
+    r = fma(r, u, 1.0 / 3.0);
+    return fma(r, u, 1.0);
+}
+__device__ __forceinline__ double series_G(double u) {
+    // coefficients of 1/F(u): g_k = -sum_{i=1..k} g_{k-i}/(2i+1), g_0 = 1
+    double r = -25865068.0 / 1915538625.0;
+    r = fma(r, u, -10719068.0 / 638512875.0);
+    r = fma(r, u, -10196.0 / 467775.0);
+    r = fma(r, u, -428.0 / 14175.0);
+    r = fma(r, u, -44.0 / 945.0);
+    r = fma(r, u, -4.0 / 45.0);
+    r = fma(r, u, -1.0 / 3.0);
+    return fma(r, u, 1.0);
+}
+
+constexpr double LOGMEAN_U = 1e-2;
+
+struct Node {
+    double rho, u1, u2, u3, beta, lrho, lbeta, k;  // beta = rho / (2P) = 1/(2RT), k = |U|^2
+};
+
+__device__ __forceinline__ void primitives(const double q[5], double gm1, Node &n, double &P,
+                                           bool &ok) {
+    n.rho = q[0];
+    const double ir = rcp(q[0]);
+    n.u1 = q[1] * ir;
+    n.u2 = q[2] * ir;
+    n.u3 = q[3] * ir;
+    n.k = n.u1 * n.u1 + n.u2 * n.u2 + n.u3 * n.u3;
+    P = gm1 * (q[4] - 0.5 * q[0] * n.k);
+    ok = (q[0] > 0.0) && (P > 0.0) && isfinite(q[4]) && isfinite(n.k);
+    n.beta = ok ? 0.5 * q[0] / P : 1.0;
+    n.lrho = ok ? log(q[0]) : 0.0;
+    n.lbeta = ok ? log(n.beta) : 0.0;
+}
+
+// Two-point flux F#(a, b) contracted with the vector (n0, n1, n2).
+// FLUX 0: Chandrashekar (entropy conservative), 1: central, 2: Kennedy-Gruber.
+template <int FLUX>
+__device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, double n1, double n2,
+                                       double gm1, double f[5]) {
+    const double ub1 = 0.5 * (a.u1 + b.u1), ub2 = 0.5 * (a.u2 + b.u2), ub3 = 0.5 * (a.u3 + b.u3);
+    const double un = ub1 * n0 + ub2 * n1 + ub3 * n2;
+    if constexpr (FLUX == 0) {
+        const double sr = a.rho + b.rho, dr = a.rho - b.rho;
+        const double isr = rcp(sr);
+        const double zr = dr * isr, ur = zr * zr;
+        double rho_hat;
+        if (ur < LOGMEAN_U) rho_hat = 0.5 * sr * series_G(ur);
+        else rho_hat = dr * rcp(a.lrho - b.lrho);
+        const double sb = a.beta + b.beta, db = a.beta - b.beta;
+        const double isb = rcp(sb);
+        const double zb = db * isb, ub = zb * zb;
+        double ibeta_hat;
+        if (ub < LOGMEAN_U) ibeta_hat = 2.0 * isb * series_F(ub);
+        else ibeta_hat = (a.lbeta - b.lbeta) * rcp(db);
+        const double pt = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
+        const double fr = rho_hat * un;
+        f[0] = fr;
+        f[1] = fma(fr, ub1, pt * n0);
+        f[2] = fma(fr, ub2, pt * n1);
+        f[3] = fma(fr, ub3, pt * n2);
+        const double kb = 0.5 * (a.k + b.k);
+        const double ubsq = ub1 * ub1 + ub2 * ub2 + ub3 * ub3;
+        f[4] = fma(fr, (0.5 / gm1) * ibeta_hat - 0.5 * kb + ubsq, pt * un);
+    } else {
+        // pressures and specific total energies from the staged node data
+        const double Pa = 0.5 * a.rho / a.beta, Pb = 0.5 * b.rho / b.beta;
+        if constexpr (FLUX == 1) {
+            const double una = a.u1 * n0 + a.u2 * n1 + a.u3 * n2;
+            const double unb = b.u1 * n0 + b.u2 * n1 + b.u3 * n2;
+            const double ma = a.rho * una, mb = b.rho * unb;
+            const double Ha = (Pa / gm1 + 0.5 * a.rho * a.k + Pa) / a.rho;
+            const double Hb = (Pb / gm1 + 0.5 * b.rho * b.k + Pb) / b.rho;
+            f[0] = 0.5 * (ma + mb);
+            f[1] = 0.5 * (ma * a.u1 + mb * b.u1 + (Pa + Pb) * n0);
+            f[2] = 0.5 * (ma * a.u2 + mb * b.u2 + (Pa + Pb) * n1);
+            f[3] = 0.5 * (ma * a.u3 + mb * b.u3 + (Pa + Pb) * n2);
+            f[4] = 0.5 * (ma * Ha + mb * Hb);
+        } else {
+            const double rb = 0.5 * (a.rho + b.rho), Pbar = 0.5 * (Pa + Pb);
+            const double Ea = Pa / (gm1 * a.rho) + 0.5 * a.k, Eb = Pb / (gm1 * b.rho) + 0.5 * b.k;
+            const double fr = rb * un;
+            f[0] = fr;
+            f[1] = fr * ub1 + Pbar * n0;
+            f[2] = fr * ub2 + Pbar * n1;
+            f[3] = fr * ub3 + Pbar * n2;
+            f[4] = fr * 0.5 * (Ea + Eb) + Pbar * un;
+        }
+    }
+}
+
+// sum_m An_m F^V_m for the viscous flux of eq. Fv (Fourier heat flux) with stresses of eq. tau,
+// evaluated from entropy-variable gradients g[j][c] = dW_{c+1}/dx_j (c = 0..3: U/T and -1/T).
+// Returns the momentum and energy components (the mass component is zero).
+__device__ __forceinline__ void visc_flux_contract(const double g[3][4], double u1, double u2,
+                                                   double u3, double T, double mu, double kap,
+                                                   const double An[3], double out[4]) {
+    const double u[3] = {u1, u2, u3};
+    double du[3][3];  // du[k][j] = dU_k/dx_j = T (dW_{k+1}/dx_j + U_k dW_5/dx_j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) du[k][j] = T * fma(u[k], g[j][3], g[j][k]);
+    const double div = du[0][0] + du[1][1] + du[2][2];
+    const double T2k = kap * T * T;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[c] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        double tau[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            tau[i] = mu * (du[i][m] + du[m][i] - (i == m ? (2.0 / 3.0) * div : 0.0));
+        const double e = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + T2k * g[m][3];
+        out[0] = fma(An[m], tau[0], out[0]);
+        out[1] = fma(An[m], tau[1], out[1]);
+        out[2] = fma(An[m], tau[2], out[2]);
+        out[3] = fma(An[m], e, out[3]);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ int tangential_index(int l, int i1, int i2, int i3) {
+    return l == 0 ? i2 + N * i3 : (l == 1 ? i1 + N * i3 : i1 + N * i2);
+}
+
+template <int N, int EPW, bool VISC, int FLUX>
+__global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
+k_residual(const ResArgs a) {
+    constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
+    constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6, F_K = 7;
+    constexpr int F_A = 8, F_MSG = 11;
+    __shared__ double s_buf[16 * NODES];
+    __shared__ double s_D[N2];
+
+    const int tid = threadIdx.x;
+    if (tid < N2) s_D[tid] = a.D[tid];
+    const int slot = tid / N3;
+    const int ln = tid - slot * N3;
+    const long long e = (long long)blockIdx.x * EPW + slot;
+    const bool active = (tid < NODES) && (e < a.K);
+    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+    const int idx[3] = {i1, i2, i3};
+    const int stride[3] = {1, N, N2};
+    const long long nodes = a.nodes;
+    const long long g = e * N3 + ln;
+    const double gm1 = a.gamma - 1.0;
+    const double w_end = a.w_end;
+
+    // ---- node-local primitives --------------------------------------------------------------
+    double q[5];
+    double A[3][3];
+    double J = 1.0;
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q[c] = a.q[c * nodes + g];
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[l][m] = a.metric[(3 * l + m) * nodes + g];
+        J = a.jac[g];
+    } else {
+        q[0] = 1.0; q[1] = q[2] = q[3] = 0.0; q[4] = 1.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[l][m] = 0.0;
+    }
+    Node me;
+    double Pme;
+    bool ok;
+    primitives(q, gm1, me, Pme, ok);
+    if (active && !ok) atomicOr(a.status, FLAG_NONPHYSICAL);
+    if (tid < NODES) {
+        s_buf[F_RHO * NODES + tid] = me.rho;
+        s_buf[F_U1 * NODES + tid] = me.u1;
+        s_buf[F_U2 * NODES + tid] = me.u2;
+        s_buf[F_U3 * NODES + tid] = me.u3;
+        s_buf[F_B * NODES + tid] = me.beta;
+        s_buf[F_LR * NODES + tid] = me.lrho;
+        s_buf[F_LB * NODES + tid] = me.lbeta;
+        s_buf[F_K * NODES + tid] = me.k;
+    }
+
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+    // ---- inviscid volume term: -sum_l sum_j D(i_l, j_l) (A_l,i + A_l,j) . F#(q_i, q_j) ----------
+    // (the j = i terms cancel exactly against the own-flux part of the interface SAT)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (tid < NODES) {
+            s_buf[(F_A + 0) * NODES + tid] = A[l][0];
+            s_buf[(F_A + 1) * NODES + tid] = A[l][1];
+            s_buf[(F_A + 2) * NODES + tid] = A[l][2];
+        }
+        __syncthreads();
+        const int il = idx[l];
+        const int st = stride[l];
+        auto pair = [&](int b, double f[5]) {
+            const int pn = tid + (b - il) * st;
+            Node o;
+            o.rho = s_buf[F_RHO * NODES + pn];
+            o.u1 = s_buf[F_U1 * NODES + pn];
+            o.u2 = s_buf[F_U2 * NODES + pn];
+            o.u3 = s_buf[F_U3 * NODES + pn];
+            o.beta = s_buf[F_B * NODES + pn];
+            o.lrho = s_buf[F_LR * NODES + pn];
+            o.lbeta = s_buf[F_LB * NODES + pn];
+            o.k = s_buf[F_K * NODES + pn];
+            const double n0 = A[l][0] + s_buf[(F_A + 0) * NODES + pn];
+            const double n1 = A[l][1] + s_buf[(F_A + 1) * NODES + pn];
+            const double n2 = A[l][2] + s_buf[(F_A + 2) * NODES + pn];
+            flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
+            return pn;
+        };
+#pragma unroll
+        for (int r = 1; 2 * r < N; ++r) {
+            int b = il + r;
+            if (b >= N) b -= N;
+            double f[5];
+            int pn = 0;
+            if (tid < NODES) {
+                pn = pair(b, f);
+                const double dab = s_D[il * N + b], dba = s_D[b * N + il];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    acc[c] = fma(-dab, f[c], acc[c]);
+                    s_buf[(F_MSG + c) * NODES + pn] = dba * f[c];
+                }
+            }
+            __syncthreads();
+            if (tid < NODES) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] -= s_buf[(F_MSG + c) * NODES + tid];
+            }
+            __syncthreads();
+        }
+        if constexpr (N % 2 == 0) {
+            if (tid < NODES) {
+                int b = il + N / 2;
+                if (b >= N) b -= N;
+                double f[5];
+                pair(b, f);
+                const double dab = s_D[il * N + b];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] = fma(-dab, f[c], acc[c]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- inviscid interface SAT: -(s/w_end) F#(q_i, q_nu) . nbar, Lax-Friedrichs dissipation ----
+    const double isw = 1.0 / w_end;
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int il = idx[l];
+            if (il != 0 && il != N - 1) continue;
+            const int side = (il == N - 1) ? 1 : 0;
+            const double s = side ? 1.0 : -1.0;
+            const long long nb = a.nbr[e * 6 + 2 * l + side];
+            if (nb < 0 || nb >= a.K) {
+                atomicOr(a.status, FLAG_MESH);
+                continue;
+            }
+            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
+            double qn[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
+            const double An0 = a.metric[(3 * l + 0) * nodes + pg];
+            const double An1 = a.metric[(3 * l + 1) * nodes + pg];
+            const double An2 = a.metric[(3 * l + 2) * nodes + pg];
+            Node o;
+            double Pn;
+            bool okn;
+            primitives(qn, gm1, o, Pn, okn);
+            const double n0 = 0.5 * (A[l][0] + An0), n1 = 0.5 * (A[l][1] + An1),
+                         n2 = 0.5 * (A[l][2] + An2);
+            double f[5];
+            flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[c] = fma(-s * isw, f[c], acc[c]);
+            if (a.iface_diss) {
+                const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+                const double li = fabs(me.u1 * n0 + me.u2 * n1 + me.u3 * n2) +
+                                  sqrt(a.gamma * Pme / me.rho) * nn;
+                const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) +
+                                  sqrt(a.gamma * Pn / o.rho) * nn;
+                const double lam = fmax(li, lo);
+                const double cf = -0.5 * lam * isw;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] = fma(cf, q[c] - qn[c], acc[c]);
+            }
+        }
+    }
+
+    const double iJ = 1.0 / J;
+
+    if constexpr (VISC) {
+        // ---- viscous operator in entropy variables (BR1 gradient, divergence, SAT^V, IP) --------
+        const double mu = a.mu;
+        const double kap = a.mu * a.gamma * a.R / ((a.gamma - 1.0) * a.Pr);
+        const double iT = 2.0 * a.R * me.beta;  // 1/T
+        const double T = 1.0 / iT;
+        const double w[4] = {me.u1 * iT, me.u2 * iT, me.u3 * iT, -iT};
+        __syncthreads();
+        if (tid < NODES) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s_buf[c * NODES + tid] = w[c];
+        }
+        __syncthreads();
+        double th[3][4];
+        double wn_face[3][4];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) th[d][c] = 0.0;
+            if (tid < NODES) {
+                const int il = idx[d];
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const double dd = s_D[il * N + b];
+                    const int pn = tid + (b - il) * stride[d];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) th[d][c] = fma(dd, s_buf[c * NODES + pn], th[d][c]);
+                }
+            }
+        }
+        // SAT^theta = (s/(2 w_end)) (w_nu - w_i) on faces of direction d
+        double Jn_face[3], An_face[3][3], un_face[3][3], Tn_face[3];
+        bool face[3] = {false, false, false};
+        long long nbf[3] = {0, 0, 0};
+        if (active) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int il = idx[d];
+                if (il != 0 && il != N - 1) continue;
+                const int side = (il == N - 1) ? 1 : 0;
+                const double s = side ? 1.0 : -1.0;
+                const long long nb = a.nbr[e * 6 + 2 * d + side];
+                if (nb < 0 || nb >= a.K) continue;
+                face[d] = true;
+                nbf[d] = nb;
+                const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
+                double qn[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
+                const double irn = 1.0 / qn[0];
+                const double v1 = qn[1] * irn, v2 = qn[2] * irn, v3 = qn[3] * irn;
+                const double Pn = gm1 * (qn[4] - 0.5 * qn[0] * (v1 * v1 + v2 * v2 + v3 * v3));
+                const double iTn = qn[0] * a.R / Pn;
+                wn_face[d][0] = v1 * iTn;
+                wn_face[d][1] = v2 * iTn;
+                wn_face[d][2] = v3 * iTn;
+                wn_face[d][3] = -iTn;
+                un_face[d][0] = v1;
+                un_face[d][1] = v2;
+                un_face[d][2] = v3;
+                Tn_face[d] = 1.0 / iTn;
+                Jn_face[d] = a.jac[pg];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) An_face[d][m] = a.metric[(3 * d + m) * nodes + pg];
+                const double cf = 0.5 * s * isw;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) th[d][c] = fma(cf, wn_face[d][c] - w[c], th[d][c]);
+            }
+        }
+        // physical gradient g_j = sum_d A_dj theta_d / J, viscous flux, contravariant fluxes fhat_l
+        double gr[3][4];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                gr[j][c] = (A[0][j] * th[0][c] + A[1][j] * th[1][c] + A[2][j] * th[2][c]) * iJ;
+        double fh[3][4];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) visc_flux_contract(gr, me.u1, me.u2, me.u3, T, mu, kap, A[l], fh[l]);
+        // face traces of fhat_l for the neighbours' SAT^V
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int il = idx[l];
+                if (il != 0 && il != N - 1) continue;
+                const int side = (il == N - 1) ? 1 : 0;
+                const int t = tangential_index<N>(l, i1, i2, i3);
+                double *tr = a.trace + ((e * 6 + 2 * l + side) * 4) * N2 + t;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) tr[c * N2] = fh[l][c];
+            }
+        }
+        // divergence sum_l D_l fhat_l
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            __syncthreads();
+            if (tid < NODES) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s_buf[(4 + c) * NODES + tid] = fh[l][c];
+            }
+            __syncthreads();
+            if (tid < NODES) {
+                const int il = idx[l];
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const double dd = s_D[il * N + b];
+                    const int pn = tid + (b - il) * stride[l];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(dd, s_buf[(4 + c) * NODES + pn], acc[c + 1]);
+                }
+            }
+        }
+        // own part of SAT^V and interior penalty
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!face[l]) continue;
+                const double s = (idx[l] == N - 1) ? 1.0 : -1.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c + 1] = fma(-0.5 * s * isw, fh[l][c], acc[c + 1]);
+                if (a.eta != 0.0) {
+                    double dw[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dw[c] = w[c] - wn_face[l][c];
+                    double gi[3][4], gn[3][4];
+                    const double iJn = 1.0 / Jn_face[l];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            gi[j][c] = A[l][j] * dw[c] * iJ;
+                            gn[j][c] = An_face[l][j] * dw[c] * iJn;
+                        }
+                    double pi_[4], pn_[4];
+                    visc_flux_contract(gi, me.u1, me.u2, me.u3, T, mu, kap, A[l], pi_);
+                    visc_flux_contract(gn, un_face[l][0], un_face[l][1], un_face[l][2], Tn_face[l], mu,
+                                       kap, An_face[l], pn_);
+                    const double cf = -0.5 * a.eta * isw;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cf, pi_[c] + pn_[c], acc[c + 1]);
+                }
+            }
+        }
+        (void)nbf;
+    }
+
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) a.out[c * nodes + g] = acc[c] * iJ;
+    }
+}
+
+// Adds the neighbour half of SAT^V, (s/(2 w_end)) fhat_l,nu / J, at face nodes.
+template <int N>
+__global__ void __launch_bounds__(256) k_visc_fixup(const ResArgs a) {
+    constexpr int N2 = N * N, N3 = N * N * N;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nodes) return;
+    const long long e = g / N3;
+    const int ln = (int)(g - e * N3);
+    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+    const int idx[3] = {i1, i2, i3};
+    bool any = false;
+    double add[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int il = idx[l];
+        if (il != 0 && il != N - 1) continue;
+        const int side = (il == N - 1) ? 1 : 0;
+        const double s = side ? 1.0 : -1.0;
+        const long long nb = a.nbr[e * 6 + 2 * l + side];
+        if (nb < 0 || nb >= a.K) continue;
+        const int t = tangential_index<N>(l, i1, i2, i3);
+        const double *tr = a.trace + ((nb * 6 + 2 * l + (1 - side)) * 4) * N2 + t;
+        const double cf = 0.5 * s / a.w_end;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) add[c] = fma(cf, tr[c * N2], add[c]);
+        any = true;
+    }
+    if (!any) return;
+    const double iJ = 1.0 / a.jac[g];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.out[(c + 1) * a.nodes + g] += add[c] * iJ;
+}
+
+__global__ void __launch_bounds__(256) k_rk_stage(const RkArgs a) {
+    const double dt = *a.dt;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const double k = a.k[i];
+        const double q = a.q[i];
+        switch (a.stage) {
+            case 0:
+                a.acc[i] = fma(dt / 6.0, k, q);
+                a.qs[i] = fma(0.5 * dt, k, q);
+                break;
+            case 1:
+                a.acc[i] = fma(dt / 3.0, k, a.acc[i]);
+                a.qs[i] = fma(0.5 * dt, k, q);
+                break;
+            case 2:
+                a.acc[i] = fma(dt / 3.0, k, a.acc[i]);
+                a.qs[i] = fma(dt, k, q);
+                break;
+            default:
+                a.q[i] = fma(dt / 6.0, k, a.acc[i]);
+                break;
+        }
+    }
+}
+
+// Curl-form metrics J dxi_i/dx_n = -[curl_xi(X_l grad_xi X_m)]_i, (n, m, l) cyclic, and
+// J = det(dx/dxi), with every derivative the collocation derivative D along a line of the element.
+template <int N>
+__global__ void __launch_bounds__(NT_OF(N * N * N))
+k_metrics(const double *x, double *metric, double *jac, const double *D, long long K) {
+    constexpr int N2 = N * N, N3 = N * N * N;
+    __shared__ double s_x[3 * N3];
+    __shared__ double s_V[3 * N3];
+    __shared__ double s_D[N2];
+    const int tid = threadIdx.x;
+    const long long e = blockIdx.x;
+    const long long nodes = K * N3;
+    if (tid < N2) s_D[tid] = D[tid];
+    const bool act = tid < N3;
+    const int i1 = tid % N, i2 = (tid / N) % N, i3 = tid / N2;
+    const int idx[3] = {i1, i2, i3};
+    const int stride[3] = {1, N, N2};
+    const long long g = e * N3 + tid;
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) s_x[m * N3 + tid] = x[m * nodes + g];
+    }
+    __syncthreads();
+    auto dline = [&](const double *arr, int dir) {
+        double r = 0.0;
+        const int il = idx[dir];
+#pragma unroll
+        for (int b = 0; b < N; ++b) r = fma(s_D[il * N + b], arr[tid + (b - il) * stride[dir]], r);
+        return r;
+    };
+    double dx[3][3];  // dx[m][i] = dx_m/dxi_i
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dx[m][i] = dline(s_x + m * N3, i);
+        const double Jv = dx[0][0] * (dx[1][1] * dx[2][2] - dx[1][2] * dx[2][1]) -
+                          dx[0][1] * (dx[1][0] * dx[2][2] - dx[1][2] * dx[2][0]) +
+                          dx[0][2] * (dx[1][0] * dx[2][1] - dx[1][1] * dx[2][0]);
+        jac[g] = Jv;
+    }
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const int m = (n + 1) % 3, l = (n + 2) % 3;
+        __syncthreads();
+        if (act) {
+            const double xl = s_x[l * N3 + tid];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) s_V[i * N3 + tid] = xl * dx[m][i];
+        }
+        __syncthreads();
+        if (act) {
+            const double c0 = dline(s_V + 2 * N3, 1) - dline(s_V + 1 * N3, 2);
+            const double c1 = dline(s_V + 0 * N3, 2) - dline(s_V + 2 * N3, 0);
+            const double c2 = dline(s_V + 1 * N3, 0) - dline(s_V + 0 * N3, 1);
+            metric[(3 * 0 + n) * nodes + g] = -c0;
+            metric[(3 * 1 + n) * nodes + g] = -c1;
+            metric[(3 * 2 + n) * nodes + g] = -c2;
+        }
+    }
+}
+
+template <int N, int EPW, bool VISC, int FLUX>
+int launch_res_t(const ResArgs &a, hipStream_t s) {
+    constexpr int NT = NT_OF(EPW * N * N * N);
+    const long long blocks = (a.K + EPW - 1) / EPW;
+    KernelTimer &tm = residual_timer();
+    if (tm.enabled) hipEventRecord(tm.begin, s);
+    hipLaunchKernelGGL((k_residual<N, EPW, VISC, FLUX>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (tm.enabled) hipEventRecord(tm.end, s);
+    if (VISC) {
+        const long long nb = (a.nodes + 255) / 256;
+        hipLaunchKernelGGL((k_visc_fixup<N>), dim3((unsigned)nb), dim3(256), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return -1;
+    }
+    return 0;
+}
+
+template <int N, int EPW>
+int launch_res_n(const ResArgs &a, hipStream_t s) {
+    const bool visc = a.mu != 0.0;
+    switch (a.two_point) {
+        case 0: return visc ? launch_res_t<N, EPW, true, 0>(a, s) : launch_res_t<N, EPW, false, 0>(a, s);
+        case 1: return visc ? launch_res_t<N, EPW, true, 1>(a, s) : launch_res_t<N, EPW, false, 1>(a, s);
+        case 2: return visc ? launch_res_t<N, EPW, true, 2>(a, s) : launch_res_t<N, EPW, false, 2>(a, s);
+        default: return -1;
+    }
+}
+
+}  // namespace
+
+KernelTimer &residual_timer() {
+    static KernelTimer t;
+    return t;
+}
+
+int launch_residual(int p, const ResArgs &a, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_res_n<2, 8>(a, s);
+        case 2: return launch_res_n<3, 2>(a, s);
+        case 3: return launch_res_n<4, 1>(a, s);
+        case 4: return launch_res_n<5, 1>(a, s);
+        case 5: return launch_res_n<6, 1>(a, s);
+        case 6: return launch_res_n<7, 1>(a, s);
+        case 7: return launch_res_n<8, 1>(a, s);
+        case 8: return launch_res_n<9, 1>(a, s);
+        default: return -1;
+    }
+}
+
+int launch_rk_stage(const RkArgs &a, hipStream_t s) {
+    long long blocks = (a.n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_rk_stage, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_metrics(int p, long long K, const double *x, double *metric, double *jac,
+                   const double *D, hipStream_t s) {
+#define SBP_MET(NN)                                                                              \
+    hipLaunchKernelGGL((k_metrics<NN>), dim3((unsigned)K), dim3(NT_OF(NN * NN * NN)), 0, s, x,   \
+                       metric, jac, D, K);                                                        \
+    break;
+    switch (p) {
+        case 1: SBP_MET(2)
+        case 2: SBP_MET(3)
+        case 3: SBP_MET(4)
+        case 4: SBP_MET(5)
+        case 5: SBP_MET(6)
+        case 6: SBP_MET(7)
+        case 7: SBP_MET(8)
+        case 8: SBP_MET(9)
+        case 9: SBP_MET(10)
+        default: return -1;
+    }
+#undef SBP_MET
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace sbp

@@ -1,0 +1,66 @@
+"""The C-ABI library loads on a host without a GPU and exports every symbol of include/sbp.h;
+host-only entry points (the 1-D operator, argument checks) work without a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1911_10966_amd as P
+from paper_1911_10966_amd import _lib
+from oracle import operators
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sbp.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*\*?(sbp_\w+)\s*\(", src, re.M)))
+
+
+def test_header_matches_binding():
+    assert declared_functions() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.sbp_version() >= 100
+
+
+@pytest.mark.parametrize("p", list(range(1, 16)))
+def test_lgl_operator_matches_oracle(p):
+    x, w, D = P.lgl_operator(p)
+    o = operators.SBP1D(p)
+    assert np.abs(x - o.x).max() < 1e-15
+    assert np.abs(w - o.w).max() < 1e-15
+    assert np.abs(D - o.D).max() < 1e-13 * p * p
+
+
+def test_lgl_operator_rejects_bad_degree():
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert P.lib().sbp_lgl_operator(0, None, None, None) == _lib.SBP_ERR_DEGREE
+    assert P.lib().sbp_lgl_operator(16, None, None, None) == _lib.SBP_ERR_DEGREE
+
+
+def test_argument_errors_on_host():
+    L = P.lib()
+    pr = _lib.sbp_problem(3, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0)
+    arr = (_lib.sbp_problem * 1)(pr)
+    assert L.sbp_workspace_bytes(arr, 1) > 0
+    bad = (_lib.sbp_problem * 1)(_lib.sbp_problem(9, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0))
+    assert L.sbp_workspace_bytes(bad, 1) == 0
+    assert L.sbp_residual(bad, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_DEGREE
+    # workspace too small
+    assert L.sbp_residual(arr, 1, 64, 128, 256, 8, None) == _lib.SBP_ERR_WORKSPACE
+    # aliasing output
+    assert L.sbp_residual(arr, 1, 64, 64, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
+    # misaligned metric
+    mis = (_lib.sbp_problem * 1)(_lib.sbp_problem(3, 1, 8, 64, 65, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0))
+    assert L.sbp_residual(mis, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
+    # bad option
+    opt = (_lib.sbp_problem * 1)(_lib.sbp_problem(3, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 7, 0))
+    assert L.sbp_residual(opt, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
+    assert P.lib().sbp_error_string(_lib.SBP_ERR_WORKSPACE).decode().startswith("workspace")

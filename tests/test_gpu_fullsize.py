@@ -1,0 +1,74 @@
+"""Full-size workloads in the launch configuration the benchmark times: sampled elements against
+the oracle, and properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1911_10966_amd as P
+import workloads as W
+from gpu_helpers import DEV, require_gpu
+from helpers import rel_err
+from oracle import geometry, operators, residual as R
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def build(name):
+    prob = W.config(name)
+    sbp = operators.SBP1D(prob.p)
+    x = W.coords(prob, sbp.x, device=DEV)
+    q = W.state(prob, x)
+    xc = x.cpu().numpy()
+    metric = geometry.curl_metrics(xc, sbp.D)
+    jac = geometry.jacobian(xc, sbp.D)
+    nbr = W.neighbours(prob.E)
+    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(nbr, device=DEV),
+                   metric=torch.as_tensor(metric.reshape(9, -1), device=DEV),
+                   jac=torch.as_tensor(jac.reshape(-1), device=DEV), gamma=prob.gamma, R=prob.R,
+                   mu=prob.mu, Pr=prob.Pr, eta=prob.eta, iface_diss=prob.iface_diss,
+                   two_point=prob.two_point)
+    return prob, sbp, q, metric, jac, nbr, dp
+
+
+@pytest.mark.parametrize("name", ["ns_tgv_p4_e32", "ns_p7_e16", "vjp_p4_e16"])
+def test_sampled_elements_match_oracle(name):
+    require_gpu()
+    print(f"full-size {name}", flush=True)
+    prob, sbp, qd, metric, jac, nbr, dp = build(name)
+    ps = P.ProblemSet([dp])
+    out = ps.residual(qd.reshape(-1).contiguous()).cpu().numpy().reshape(qd.shape)
+    assert ps.status() == 0
+    q = qd.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(7))
+    sel = np.unique(np.concatenate([[0, prob.K - 1], rng.integers(0, prob.K, 14)]))
+    ref = R.residual(q, metric, jac, nbr, sbp, R.Params.of(prob), elems=sel)
+    # FP64 rounding floor of this workload: the double oracle against the long-double oracle on
+    # the same inputs.  At low Mach numbers the residual is a strong cancellation of the pressure
+    # terms and this floor exceeds 1e-12; the GPU must then be as accurate as the FP64 oracle.
+    LD = np.longdouble
+    ref_ld = R.residual(q.astype(LD), metric.astype(LD), jac.astype(LD), nbr,
+                        operators.SBP1D(prob.p, LD), R.Params.of(prob), elems=sel)
+    floor = rel_err(ref, ref_ld)
+    err_ld = rel_err(out[:, sel], ref_ld)
+    err = rel_err(out[:, sel], ref)
+    print(f"{name}: gpu-vs-oracle {err:.2e}  gpu-vs-longdouble {err_ld:.2e}  fp64 floor {floor:.2e}")
+    assert err_ld <= max(TOL, 4.0 * floor)
+    assert err <= max(TOL, 4.0 * floor)
+
+
+def test_rk4_conserves_totals_full_size():
+    """One RK4 step of the Taylor-Green workload conserves sum_nodes w J q_c (periodic box)."""
+    require_gpu()
+    prob, sbp, qd, metric, jac, nbr, dp = build("ns_tgv_p4_e32")
+    ps = P.ProblemSet([dp])
+    w = torch.as_tensor(np.einsum("i,j,k->ijk", sbp.w, sbp.w, sbp.w), device=DEV)
+    wj = (w[None] * torch.as_tensor(jac, device=DEV)).reshape(-1)
+    q = qd.reshape(5, -1).contiguous()
+    before = (q * wj).sum(1)
+    dt = W.cfl_dt(prob, W.coords(prob, sbp.x, device=DEV))
+    ps.rk_step(q.reshape(-1), torch.tensor([dt], dtype=torch.float64, device=DEV), 1)
+    after = (q * wj).sum(1)
+    scale = (q.abs() * wj).sum(1)
+    assert ps.status() == 0
+    assert torch.all((after - before).abs() <= 1e-13 * scale)
