@@ -107,7 +107,11 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
                 int32_t n_steps, void *ws, size_t ws_bytes, void *stream);
 
 /* Vector-Jacobian product qbar = (d(dq/dt)/dq)^T gbar of the residual of sbp_residual, with each
- * element recomputing its forward intermediates.  q, gbar, qbar: device, same layout as q. */
+ * element recomputing its forward intermediates (no two-point fluxes are stored) and interface
+ * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
+ * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0); other fluxes give
+ * SBP_ERR_ARG.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
+ * in the interface dissipation takes the own side on ties. */
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
                      double *qbar, void *ws, size_t ws_bytes, void *stream);
 

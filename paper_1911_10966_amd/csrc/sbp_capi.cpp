@@ -146,10 +146,12 @@ long long nodes_of(const sbp_problem &pr) {
     return pr.n_elem * N * N * N;
 }
 
-// Workspace layout: [flags | per-problem viscous traces | RK buffers acc, qs, k].
+// Workspace layout: [flags | per-problem viscous traces | per-problem VJP gradient cotangents |
+// RK buffers acc, qs, k].
 struct Layout {
     size_t flags = 0;
     std::vector<size_t> trace;  // offset per problem (0 if inviscid)
+    std::vector<size_t> thb;    // offset per problem (0 if inviscid)
     size_t rk = 0;              // offset of the RK block
     size_t total_state = 0;     // doubles in one state-sized buffer
     size_t bytes = 0;
@@ -159,12 +161,15 @@ Layout layout_of(const sbp_problem *probs, int n) {
     Layout L;
     size_t off = align_up(sizeof(int) * 16);
     L.trace.resize(n, 0);
+    L.thb.resize(n, 0);
     size_t states = 0;
     for (int b = 0; b < n; ++b) {
         const long long N = probs[b].p + 1;
         if (probs[b].mu > 0.0) {
             L.trace[b] = off;
             off += align_up(sizeof(double) * (size_t)probs[b].n_elem * 6 * 4 * N * N);
+            L.thb[b] = off;
+            off += align_up(sizeof(double) * 12 * (size_t)nodes_of(probs[b]));
         }
         states += 5 * (size_t)nodes_of(probs[b]);
     }
@@ -212,12 +217,12 @@ sbp::ResArgs res_args(const sbp_problem &pr, const double *q, double *out, char 
 }
 
 int residual_all(const sbp_problem *probs, int n, const double *q, double *out, char *ws,
-                 const Layout &L, hipStream_t s) {
+                 const Layout &L, hipStream_t s, bool fixup = true) {
     size_t off = 0;
     for (int b = 0; b < n; ++b) {
         sbp::ResArgs a = res_args(probs[b], q + off, out + off, ws, L.trace[b]);
         if (a.D == nullptr) return SBP_ERR_HIP;
-        if (sbp::launch_residual(probs[b].p, a, s) != 0) return SBP_ERR_HIP;
+        if (sbp::launch_residual(probs[b].p, a, s, fixup) != 0) return SBP_ERR_HIP;
         off += 5 * (size_t)nodes_of(probs[b]);
     }
     return SBP_OK;
@@ -231,13 +236,14 @@ int rk_step_launches(const sbp_problem *probs, int n, double *q, const double *d
     double *k = reinterpret_cast<double *>(ws + L.rk + 2 * align_up(sizeof(double) * L.total_state));
     for (int stage = 0; stage < 4; ++stage) {
         const double *src = stage == 0 ? q : qs;
-        const int rc = residual_all(probs, n, src, k, ws, L, s);
+        const int rc = residual_all(probs, n, src, k, ws, L, s, false);
         if (rc != SBP_OK) return rc;
         size_t off = 0;
         for (int b = 0; b < n; ++b) {
             const long long cnt = 5 * nodes_of(probs[b]);
+            sbp::ResArgs a = res_args(probs[b], src + off, k + off, ws, L.trace[b]);
             sbp::RkArgs r{q + off, acc + off, qs + off, k + off, dt + b, cnt, stage};
-            if (sbp::launch_rk_stage(r, s) != 0) return SBP_ERR_HIP;
+            if (sbp::launch_rk_fixup_stage(probs[b].p, a, r, s) != 0) return SBP_ERR_HIP;
             off += cnt;
         }
     }
@@ -364,8 +370,42 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
 
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
                      double *qbar, void *ws, size_t ws_bytes, void *stream) {
-    (void)probs; (void)n_prob; (void)q; (void)gbar; (void)qbar; (void)ws; (void)ws_bytes; (void)stream;
-    return SBP_ERR_ARG;
+    Layout L;
+    int rc = validate(probs, n_prob, ws, ws_bytes, L);
+    if (rc != SBP_OK) return rc;
+    if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
+        return SBP_ERR_ARG;
+    for (int b = 0; b < n_prob; ++b)
+        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR) return SBP_ERR_ARG;
+    char *w = static_cast<char *>(ws);
+    size_t off = 0;
+    for (int b = 0; b < n_prob; ++b) {
+        const sbp_problem &pr = probs[b];
+        const int N = pr.p + 1;
+        sbp::VjpArgs a{};
+        a.q = q + off;
+        a.gbar = gbar + off;
+        a.qbar = qbar + off;
+        a.metric = pr.metric;
+        a.jac = pr.jac;
+        a.nbr = pr.nbr;
+        a.thb = pr.mu > 0.0 ? reinterpret_cast<double *>(w + L.thb[b]) : nullptr;
+        a.status = reinterpret_cast<int *>(w);
+        a.D = device_D(pr.p);
+        if (a.D == nullptr) return SBP_ERR_HIP;
+        a.K = pr.n_elem;
+        a.nodes = pr.n_elem * (long long)N * N * N;
+        a.gamma = pr.gamma;
+        a.R = pr.R;
+        a.mu = pr.mu;
+        a.Pr = pr.Pr;
+        a.eta = pr.eta;
+        a.w_end = host_op(pr.p).w[0];
+        a.iface_diss = pr.iface_diss;
+        if (sbp::launch_vjp(pr.p, a, (hipStream_t)stream) != 0) return SBP_ERR_HIP;
+        off += 5 * (size_t)nodes_of(pr);
+    }
+    return SBP_OK;
 }
 
 int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,

@@ -38,7 +38,10 @@ struct RkArgs {
     int stage;
 };
 
-int launch_residual(int p, const ResArgs &a, hipStream_t s);
+// Main residual kernel; with fixup the neighbour half of SAT^V is added by a second kernel,
+// without it the caller must apply it (launch_rk_fixup_stage does, for RK stages).
+int launch_residual(int p, const ResArgs &a, hipStream_t s, bool fixup = true);
+int launch_rk_fixup_stage(int p, const ResArgs &a, const RkArgs &r, hipStream_t s);
 
 // Optional event timing of the main residual kernel (see sbp_profile in the C ABI).
 struct KernelTimer {
@@ -47,6 +50,25 @@ struct KernelTimer {
 };
 KernelTimer &residual_timer();
 int launch_rk_stage(const RkArgs &a, hipStream_t s);
+
+// Vector-Jacobian product of the residual (Chandrashekar flux) for one problem.
+struct VjpArgs {
+    const double *q;       // SoA [5][nodes]
+    const double *gbar;    // cotangent of dq/dt, SoA [5][nodes]
+    double *qbar;          // result, SoA [5][nodes]
+    const double *metric;
+    const double *jac;
+    const int32_t *nbr;
+    double *thb;           // cotangents of the BR1 gradients, [3][4][nodes] (mu > 0 only)
+    int *status;
+    const double *D;
+    long long K;
+    long long nodes;
+    double gamma, R, mu, Pr, eta;
+    double w_end;
+    int iface_diss;
+};
+int launch_vjp(int p, const VjpArgs &a, hipStream_t s);
 int launch_metrics(int p, long long K, const double *x, double *metric, double *jac,
                    const double *D, hipStream_t s);
 

@@ -7,161 +7,10 @@
 // sum over each line uses the symmetry of the two-point flux: in round r a node evaluates the pair
 // with the node r places further along the line (cyclically), keeps D(a,b) f and hands D(b,a) f to
 // its partner through an LDS mailbox, so every pair is evaluated once.
-#include "sbp_internal.h"
-
-#include <math.h>
+#include "sbp_device.h"
 
 namespace sbp {
 namespace {
-
-constexpr int NT_OF(int nodes) { return ((nodes + 63) / 64) * 64; }
-
-// Reciprocal: hardware estimate refined by two Newton steps (a few ulp; no IEEE fixup needed
-// for the strictly positive, finite operands used here).
-__device__ __forceinline__ double rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-// With z = (a-b)/(a+b) and u = z^2:  log(a/b) = 2 artanh z = 2 z F(u),  F(u) = sum_k u^k/(2k+1),
-// so the logarithmic mean is (a+b)/(2 F(u)) and its inverse 2 F(u)/(a+b).  For u < 1e-2 the
-// series below (F through u^7, G = 1/F through u^7) are accurate to < 1e-17 relative.
-__device__ __forceinline__ double series_F(double u) {
-    double r = 1.0 / 15.0;
-    r = fma(r, u, 1.0 / 13.0);
-    r = fma(r, u, 1.0 / 11.0);
-    r = fma(r, u, 1.0 / 9.0);
-    r = fma(r, u, 1.0 / 7.0);
-    r = fma(r, u, 1.0 / 5.0);
-    r = fma(r, u, 1.0 / 3.0);
-    return fma(r, u, 1.0);
-}
-__device__ __forceinline__ double series_G(double u) {
-    // coefficients of 1/F(u): g_k = -sum_{i=1..k} g_{k-i}/(2i+1), g_0 = 1
-    double r = -25865068.0 / 1915538625.0;
-    r = fma(r, u, -10719068.0 / 638512875.0);
-    r = fma(r, u, -10196.0 / 467775.0);
-    r = fma(r, u, -428.0 / 14175.0);
-    r = fma(r, u, -44.0 / 945.0);
-    r = fma(r, u, -4.0 / 45.0);
-    r = fma(r, u, -1.0 / 3.0);
-    return fma(r, u, 1.0);
-}
-
-constexpr double LOGMEAN_U = 1e-2;
-
-struct Node {
-    double rho, u1, u2, u3, beta, lrho, lbeta, k;  // beta = rho / (2P) = 1/(2RT), k = |U|^2
-};
-
-__device__ __forceinline__ void primitives(const double q[5], double gm1, Node &n, double &P,
-                                           bool &ok) {
-    n.rho = q[0];
-    const double ir = rcp(q[0]);
-    n.u1 = q[1] * ir;
-    n.u2 = q[2] * ir;
-    n.u3 = q[3] * ir;
-    n.k = n.u1 * n.u1 + n.u2 * n.u2 + n.u3 * n.u3;
-    P = gm1 * (q[4] - 0.5 * q[0] * n.k);
-    ok = (q[0] > 0.0) && (P > 0.0) && isfinite(q[4]) && isfinite(n.k);
-    n.beta = ok ? 0.5 * q[0] / P : 1.0;
-    n.lrho = ok ? log(q[0]) : 0.0;
-    n.lbeta = ok ? log(n.beta) : 0.0;
-}
-
-// Two-point flux F#(a, b) contracted with the vector (n0, n1, n2).
-// FLUX 0: Chandrashekar (entropy conservative), 1: central, 2: Kennedy-Gruber.
-template <int FLUX>
-__device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, double n1, double n2,
-                                       double gm1, double f[5]) {
-    const double ub1 = 0.5 * (a.u1 + b.u1), ub2 = 0.5 * (a.u2 + b.u2), ub3 = 0.5 * (a.u3 + b.u3);
-    const double un = ub1 * n0 + ub2 * n1 + ub3 * n2;
-    if constexpr (FLUX == 0) {
-        const double sr = a.rho + b.rho, dr = a.rho - b.rho;
-        const double isr = rcp(sr);
-        const double zr = dr * isr, ur = zr * zr;
-        double rho_hat;
-        if (ur < LOGMEAN_U) rho_hat = 0.5 * sr * series_G(ur);
-        else rho_hat = dr * rcp(a.lrho - b.lrho);
-        const double sb = a.beta + b.beta, db = a.beta - b.beta;
-        const double isb = rcp(sb);
-        const double zb = db * isb, ub = zb * zb;
-        double ibeta_hat;
-        if (ub < LOGMEAN_U) ibeta_hat = 2.0 * isb * series_F(ub);
-        else ibeta_hat = (a.lbeta - b.lbeta) * rcp(db);
-        const double pt = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
-        const double fr = rho_hat * un;
-        f[0] = fr;
-        f[1] = fma(fr, ub1, pt * n0);
-        f[2] = fma(fr, ub2, pt * n1);
-        f[3] = fma(fr, ub3, pt * n2);
-        const double kb = 0.5 * (a.k + b.k);
-        const double ubsq = ub1 * ub1 + ub2 * ub2 + ub3 * ub3;
-        f[4] = fma(fr, (0.5 / gm1) * ibeta_hat - 0.5 * kb + ubsq, pt * un);
-    } else {
-        // pressures and specific total energies from the staged node data
-        const double Pa = 0.5 * a.rho / a.beta, Pb = 0.5 * b.rho / b.beta;
-        if constexpr (FLUX == 1) {
-            const double una = a.u1 * n0 + a.u2 * n1 + a.u3 * n2;
-            const double unb = b.u1 * n0 + b.u2 * n1 + b.u3 * n2;
-            const double ma = a.rho * una, mb = b.rho * unb;
-            const double Ha = (Pa / gm1 + 0.5 * a.rho * a.k + Pa) / a.rho;
-            const double Hb = (Pb / gm1 + 0.5 * b.rho * b.k + Pb) / b.rho;
-            f[0] = 0.5 * (ma + mb);
-            f[1] = 0.5 * (ma * a.u1 + mb * b.u1 + (Pa + Pb) * n0);
-            f[2] = 0.5 * (ma * a.u2 + mb * b.u2 + (Pa + Pb) * n1);
-            f[3] = 0.5 * (ma * a.u3 + mb * b.u3 + (Pa + Pb) * n2);
-            f[4] = 0.5 * (ma * Ha + mb * Hb);
-        } else {
-            const double rb = 0.5 * (a.rho + b.rho), Pbar = 0.5 * (Pa + Pb);
-            const double Ea = Pa / (gm1 * a.rho) + 0.5 * a.k, Eb = Pb / (gm1 * b.rho) + 0.5 * b.k;
-            const double fr = rb * un;
-            f[0] = fr;
-            f[1] = fr * ub1 + Pbar * n0;
-            f[2] = fr * ub2 + Pbar * n1;
-            f[3] = fr * ub3 + Pbar * n2;
-            f[4] = fr * 0.5 * (Ea + Eb) + Pbar * un;
-        }
-    }
-}
-
-// sum_m An_m F^V_m for the viscous flux of eq. Fv (Fourier heat flux) with stresses of eq. tau,
-// evaluated from entropy-variable gradients g[j][c] = dW_{c+1}/dx_j (c = 0..3: U/T and -1/T).
-// Returns the momentum and energy components (the mass component is zero).
-__device__ __forceinline__ void visc_flux_contract(const double g[3][4], double u1, double u2,
-                                                   double u3, double T, double mu, double kap,
-                                                   const double An[3], double out[4]) {
-    const double u[3] = {u1, u2, u3};
-    double du[3][3];  // du[k][j] = dU_k/dx_j = T (dW_{k+1}/dx_j + U_k dW_5/dx_j)
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) du[k][j] = T * fma(u[k], g[j][3], g[j][k]);
-    const double div = du[0][0] + du[1][1] + du[2][2];
-    const double T2k = kap * T * T;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) out[c] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        double tau[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            tau[i] = mu * (du[i][m] + du[m][i] - (i == m ? (2.0 / 3.0) * div : 0.0));
-        const double e = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + T2k * g[m][3];
-        out[0] = fma(An[m], tau[0], out[0]);
-        out[1] = fma(An[m], tau[1], out[1]);
-        out[2] = fma(An[m], tau[2], out[2]);
-        out[3] = fma(An[m], e, out[3]);
-    }
-}
-
-template <int N>
-__device__ __forceinline__ int tangential_index(int l, int i1, int i2, int i3) {
-    return l == 0 ? i2 + N * i3 : (l == 1 ? i1 + N * i3 : i1 + N * i2);
-}
 
 template <int N, int EPW, bool VISC, int FLUX>
 __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
@@ -176,7 +25,7 @@ k_residual(const ResArgs a) {
     if (tid < N2) s_D[tid] = a.D[tid];
     const int slot = tid / N3;
     const int ln = tid - slot * N3;
-    const long long e = (long long)blockIdx.x * EPW + slot;
+    const long long e = xcd_block(blockIdx.x, gridDim.x) * EPW + slot;
     const bool active = (tid < NODES) && (e < a.K);
     const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
     const int idx[3] = {i1, i2, i3};
@@ -520,6 +369,68 @@ __global__ void __launch_bounds__(256) k_visc_fixup(const ResArgs a) {
     for (int c = 0; c < 4; ++c) a.out[(c + 1) * a.nodes + g] += add[c] * iJ;
 }
 
+// RK4 stage update fused with the neighbour half of SAT^V (viscous problems): thread per node.
+template <int N, bool VISC>
+__global__ void __launch_bounds__(256) k_rk_fixup_stage(const ResArgs a, const RkArgs r) {
+    constexpr int N2 = N * N, N3 = N * N * N;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nodes) return;
+    double kk[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) kk[c] = r.k[c * a.nodes + g];
+    if constexpr (VISC) {
+        const long long e = g / N3;
+        const int ln = (int)(g - e * N3);
+        const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+        const int idx[3] = {i1, i2, i3};
+        bool any = false;
+        double add[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int il = idx[l];
+            if (il != 0 && il != N - 1) continue;
+            const int side = (il == N - 1) ? 1 : 0;
+            const double s = side ? 1.0 : -1.0;
+            const long long nb = a.nbr[e * 6 + 2 * l + side];
+            if (nb < 0 || nb >= a.K) continue;
+            const int t = tangential_index<N>(l, i1, i2, i3);
+            const double *tr = a.trace + ((nb * 6 + 2 * l + (1 - side)) * 4) * N2 + t;
+            const double cf = 0.5 * s / a.w_end;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) add[c] = fma(cf, tr[c * N2], add[c]);
+            any = true;
+        }
+        if (any) {
+            const double iJ = 1.0 / a.jac[g];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) kk[c + 1] = fma(add[c], iJ, kk[c + 1]);
+        }
+    }
+    const double dt = *r.dt;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const long long i = c * a.nodes + g;
+        const double q = r.q[i];
+        switch (r.stage) {
+            case 0:
+                r.acc[i] = fma(dt / 6.0, kk[c], q);
+                r.qs[i] = fma(0.5 * dt, kk[c], q);
+                break;
+            case 1:
+                r.acc[i] = fma(dt / 3.0, kk[c], r.acc[i]);
+                r.qs[i] = fma(0.5 * dt, kk[c], q);
+                break;
+            case 2:
+                r.acc[i] = fma(dt / 3.0, kk[c], r.acc[i]);
+                r.qs[i] = fma(dt, kk[c], q);
+                break;
+            default:
+                r.q[i] = fma(dt / 6.0, kk[c], r.acc[i]);
+                break;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_rk_stage(const RkArgs a) {
     const double dt = *a.dt;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -609,7 +520,7 @@ k_metrics(const double *x, double *metric, double *jac, const double *D, long lo
 }
 
 template <int N, int EPW, bool VISC, int FLUX>
-int launch_res_t(const ResArgs &a, hipStream_t s) {
+int launch_res_t(const ResArgs &a, hipStream_t s, bool fixup) {
     constexpr int NT = NT_OF(EPW * N * N * N);
     const long long blocks = (a.K + EPW - 1) / EPW;
     KernelTimer &tm = residual_timer();
@@ -617,7 +528,7 @@ int launch_res_t(const ResArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_residual<N, EPW, VISC, FLUX>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
     if (hipGetLastError() != hipSuccess) return -1;
     if (tm.enabled) hipEventRecord(tm.end, s);
-    if (VISC) {
+    if (VISC && fixup) {
         const long long nb = (a.nodes + 255) / 256;
         hipLaunchKernelGGL((k_visc_fixup<N>), dim3((unsigned)nb), dim3(256), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;
@@ -626,14 +537,24 @@ int launch_res_t(const ResArgs &a, hipStream_t s) {
 }
 
 template <int N, int EPW>
-int launch_res_n(const ResArgs &a, hipStream_t s) {
+int launch_res_n(const ResArgs &a, hipStream_t s, bool fx) {
     const bool visc = a.mu != 0.0;
     switch (a.two_point) {
-        case 0: return visc ? launch_res_t<N, EPW, true, 0>(a, s) : launch_res_t<N, EPW, false, 0>(a, s);
-        case 1: return visc ? launch_res_t<N, EPW, true, 1>(a, s) : launch_res_t<N, EPW, false, 1>(a, s);
-        case 2: return visc ? launch_res_t<N, EPW, true, 2>(a, s) : launch_res_t<N, EPW, false, 2>(a, s);
+        case 0: return visc ? launch_res_t<N, EPW, true, 0>(a, s, fx) : launch_res_t<N, EPW, false, 0>(a, s, fx);
+        case 1: return visc ? launch_res_t<N, EPW, true, 1>(a, s, fx) : launch_res_t<N, EPW, false, 1>(a, s, fx);
+        case 2: return visc ? launch_res_t<N, EPW, true, 2>(a, s, fx) : launch_res_t<N, EPW, false, 2>(a, s, fx);
         default: return -1;
     }
+}
+
+template <int N>
+int launch_rkfs_n(const ResArgs &a, const RkArgs &r, hipStream_t s) {
+    const long long nb = (a.nodes + 255) / 256;
+    if (a.mu != 0.0)
+        hipLaunchKernelGGL((k_rk_fixup_stage<N, true>), dim3((unsigned)nb), dim3(256), 0, s, a, r);
+    else
+        hipLaunchKernelGGL((k_rk_fixup_stage<N, false>), dim3((unsigned)nb), dim3(256), 0, s, a, r);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
@@ -643,16 +564,30 @@ KernelTimer &residual_timer() {
     return t;
 }
 
-int launch_residual(int p, const ResArgs &a, hipStream_t s) {
+int launch_residual(int p, const ResArgs &a, hipStream_t s, bool fixup) {
     switch (p) {
-        case 1: return launch_res_n<2, 8>(a, s);
-        case 2: return launch_res_n<3, 2>(a, s);
-        case 3: return launch_res_n<4, 1>(a, s);
-        case 4: return launch_res_n<5, 1>(a, s);
-        case 5: return launch_res_n<6, 1>(a, s);
-        case 6: return launch_res_n<7, 1>(a, s);
-        case 7: return launch_res_n<8, 1>(a, s);
-        case 8: return launch_res_n<9, 1>(a, s);
+        case 1: return launch_res_n<2, 8>(a, s, fixup);
+        case 2: return launch_res_n<3, 2>(a, s, fixup);
+        case 3: return launch_res_n<4, 1>(a, s, fixup);
+        case 4: return launch_res_n<5, 1>(a, s, fixup);
+        case 5: return launch_res_n<6, 1>(a, s, fixup);
+        case 6: return launch_res_n<7, 1>(a, s, fixup);
+        case 7: return launch_res_n<8, 1>(a, s, fixup);
+        case 8: return launch_res_n<9, 1>(a, s, fixup);
+        default: return -1;
+    }
+}
+
+int launch_rk_fixup_stage(int p, const ResArgs &a, const RkArgs &r, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_rkfs_n<2>(a, r, s);
+        case 2: return launch_rkfs_n<3>(a, r, s);
+        case 3: return launch_rkfs_n<4>(a, r, s);
+        case 4: return launch_rkfs_n<5>(a, r, s);
+        case 5: return launch_rkfs_n<6>(a, r, s);
+        case 6: return launch_rkfs_n<7>(a, r, s);
+        case 7: return launch_rkfs_n<8>(a, r, s);
+        case 8: return launch_rkfs_n<9>(a, r, s);
         default: return -1;
     }
 }

@@ -1,0 +1,711 @@
+// Vector-Jacobian product qbar = (d(dq/dt)/dq)^T gbar of the ES-C residual, written by hand.
+//
+// Every element recomputes its forward intermediates; nothing of the forward pass is stored.
+// Contributions that the forward scatters to a neighbour (interface SAT, dissipation, SAT^theta,
+// SAT^V, interior penalty) are gathered instead: an element evaluates, for its own face node,
+// the derivative of both its own and its neighbour's interface term, so no atomics are needed.
+// The BR1 operator reaches neighbours of neighbours, which takes two kernels:
+//   k_vjp_visc   cotangents of the gradients theta_a at every node (written to a buffer) and the
+//                part of qbar that comes through the state dependence of the viscous fluxes;
+//   k_vjp_main   the inviscid volume and interface terms, the interior penalty, the transposed
+//                gradient operator with its SAT (reading neighbour theta cotangents), and the map
+//                from primitive cotangents to qbar.
+// Pair terms of the flux-differencing sum use the same cyclic pairing and LDS mailbox as the
+// forward kernel; cotangents are accumulated on the node quantities (rho, U, beta) and mapped to
+// conservative variables once per node.
+#include "sbp_device.h"
+
+namespace sbp {
+namespace {
+
+__device__ __forceinline__ double series_Fp(double u) {  // dF/du
+    double r = 7.0 / 15.0;
+    r = fma(r, u, 6.0 / 13.0);
+    r = fma(r, u, 5.0 / 11.0);
+    r = fma(r, u, 4.0 / 9.0);
+    r = fma(r, u, 3.0 / 7.0);
+    r = fma(r, u, 2.0 / 5.0);
+    return fma(r, u, 1.0 / 3.0);
+}
+__device__ __forceinline__ double series_Gp(double u) {  // dG/du
+    double r = 7.0 * (-25865068.0 / 1915538625.0);
+    r = fma(r, u, 6.0 * (-10719068.0 / 638512875.0));
+    r = fma(r, u, 5.0 * (-10196.0 / 467775.0));
+    r = fma(r, u, 4.0 * (-428.0 / 14175.0));
+    r = fma(r, u, 3.0 * (-44.0 / 945.0));
+    r = fma(r, u, 2.0 * (-4.0 / 45.0));
+    return fma(r, u, -1.0 / 3.0);
+}
+
+// Cotangents of one node's quantities (rho, U, beta, log rho, log beta, |U|^2).
+struct NodeBar {
+    double rho, u1, u2, u3, beta, lrho, lbeta, k;
+};
+
+// Reverse of flux_n<0> (Chandrashekar flux contracted with a constant vector n).
+__device__ __forceinline__ void flux_n_vjp(const Node &a, const Node &b, double n0, double n1,
+                                           double n2, double gm1, const double fb[5], NodeBar &ab,
+                                           NodeBar &bb) {
+    const double ub1 = 0.5 * (a.u1 + b.u1), ub2 = 0.5 * (a.u2 + b.u2), ub3 = 0.5 * (a.u3 + b.u3);
+    const double un = ub1 * n0 + ub2 * n1 + ub3 * n2;
+    const double sr = a.rho + b.rho, dr = a.rho - b.rho;
+    const double isr = rcp(sr);
+    const double zr = dr * isr, ur = zr * zr;
+    const bool ser_r = ur < LOGMEAN_U;
+    double rho_hat, Gr = 0.0, iLr = 0.0;
+    if (ser_r) {
+        Gr = series_G(ur);
+        rho_hat = 0.5 * sr * Gr;
+    } else {
+        iLr = rcp(a.lrho - b.lrho);
+        rho_hat = dr * iLr;
+    }
+    const double sb = a.beta + b.beta, db = a.beta - b.beta;
+    const double isb = rcp(sb);
+    const double zb = db * isb, ubb = zb * zb;
+    const bool ser_b = ubb < LOGMEAN_U;
+    double ibh, Fb = 0.0, idb = 0.0;
+    if (ser_b) {
+        Fb = series_F(ubb);
+        ibh = 2.0 * isb * Fb;
+    } else {
+        idb = rcp(db);
+        ibh = (a.lbeta - b.lbeta) * idb;
+    }
+    const double pt = 0.5 * sr * isb;
+    const double fr = rho_hat * un;
+    const double c = 0.5 / gm1;
+    const double kbar = 0.5 * (a.k + b.k);
+    const double ubsq = ub1 * ub1 + ub2 * ub2 + ub3 * ub3;
+    const double E = c * ibh - 0.5 * kbar + ubsq;
+    // reverse sweep
+    const double frb = fb[0] + fb[1] * ub1 + fb[2] * ub2 + fb[3] * ub3 + fb[4] * E;
+    double u1b = fb[1] * fr + 2.0 * fb[4] * fr * ub1;
+    double u2b = fb[2] * fr + 2.0 * fb[4] * fr * ub2;
+    double u3b = fb[3] * fr + 2.0 * fb[4] * fr * ub3;
+    const double ptb = fb[1] * n0 + fb[2] * n1 + fb[3] * n2 + fb[4] * un;
+    const double Eb = fb[4] * fr;
+    const double unb = fb[4] * pt + frb * rho_hat;
+    const double rhb = frb * un;
+    const double ibhb = Eb * c;
+    const double kbb = -0.5 * Eb;
+    u1b = fma(unb, n0, u1b);
+    u2b = fma(unb, n1, u2b);
+    u3b = fma(unb, n2, u3b);
+    double srb = ptb * 0.5 * isb;
+    double isbb = ptb * 0.5 * sr;
+    double drb = 0.0, lrb = 0.0;
+    if (ser_r) {
+        srb += rhb * 0.5 * Gr;
+        const double urb = rhb * 0.5 * sr * series_Gp(ur);
+        const double zrb = 2.0 * zr * urb;
+        drb += zrb * isr;
+        const double isrb = zrb * dr;
+        srb -= isr * isr * isrb;
+    } else {
+        drb += rhb * iLr;
+        lrb = -rhb * dr * iLr * iLr;
+    }
+    double dbb = 0.0, lbb = 0.0;
+    if (ser_b) {
+        isbb += ibhb * 2.0 * Fb;
+        const double ubbb = ibhb * 2.0 * isb * series_Fp(ubb);
+        const double zbb = 2.0 * zb * ubbb;
+        dbb += zbb * isb;
+        isbb += zbb * db;
+    } else {
+        const double Lb = a.lbeta - b.lbeta;
+        lbb = ibhb * idb;
+        dbb -= ibhb * Lb * idb * idb;
+    }
+    const double sbb = -isb * isb * isbb;
+    ab.rho = srb + drb;
+    bb.rho = srb - drb;
+    ab.beta = sbb + dbb;
+    bb.beta = sbb - dbb;
+    ab.lrho = lrb;
+    bb.lrho = -lrb;
+    ab.lbeta = lbb;
+    bb.lbeta = -lbb;
+    ab.u1 = bb.u1 = 0.5 * u1b;
+    ab.u2 = bb.u2 = 0.5 * u2b;
+    ab.u3 = bb.u3 = 0.5 * u3b;
+    ab.k = bb.k = 0.5 * kbb;
+}
+
+// Folds the cotangents of log rho, log beta and |U|^2 into (rho, U, beta) of the same node.
+__device__ __forceinline__ void reduce_bar(const Node &n, const NodeBar &z, double out[5]) {
+    out[0] = z.rho + z.lrho / n.rho;
+    out[1] = fma(2.0 * n.u1, z.k, z.u1);
+    out[2] = fma(2.0 * n.u2, z.k, z.u2);
+    out[3] = fma(2.0 * n.u3, z.k, z.u3);
+    out[4] = z.beta + z.lbeta / n.beta;
+}
+
+// Reverse of the uncontracted viscous flux F^V_m[c] (m = 0..2, c = 0..3 momentum/energy) as a
+// function of the entropy-variable gradients g, the velocity and the temperature.
+__device__ __forceinline__ void visc_flux_vjp(const double g[3][4], const double u[3], double T,
+                                              double mu, double kap, const double Fb[3][4],
+                                              double gb[3][4], double ub[3], double &Tb) {
+    double du[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) du[k][j] = T * fma(u[k], g[j][3], g[j][k]);
+    const double div = du[0][0] + du[1][1] + du[2][2];
+    double dub[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dub[k][j] = 0.0;
+    double divb = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        gb[m][3] = Fb[m][3] * kap * T * T;
+        Tb += Fb[m][3] * g[m][3] * 2.0 * kap * T;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double tau = mu * (du[i][m] + du[m][i] - (i == m ? (2.0 / 3.0) * div : 0.0));
+            ub[i] += Fb[m][3] * tau;
+            const double taub = mu * (Fb[m][i] + Fb[m][3] * u[i]);
+            dub[i][m] += taub;
+            dub[m][i] += taub;
+            if (i == m) divb -= (2.0 / 3.0) * taub;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dub[k][k] += divb;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        gb[j][0] = gb[j][1] = gb[j][2] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            gb[j][k] += T * dub[k][j];
+            gb[j][3] += T * u[k] * dub[k][j];
+            ub[k] += T * g[j][3] * dub[k][j];
+            Tb += fma(u[k], g[j][3], g[j][k]) * dub[k][j];
+        }
+}
+
+// Cotangents of (rho, U, beta, P, T) of a node mapped to its conservative variables, with
+// beta = rho/(2P), T = P/(rho R), P = (gamma-1)(q_5 - rho |U|^2 / 2), U = m/rho.
+__device__ __forceinline__ void prim_vjp(const double q[5], double gm1, double R, double rb,
+                                         double ub[3], double bb, double Pb, double Tb,
+                                         double qb[5]) {
+    const double rho = q[0];
+    const double ir = 1.0 / rho;
+    const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+    const double k = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double P = gm1 * (q[4] - 0.5 * rho * k);
+    const double T = P / (rho * R);
+    const double beta = 0.5 * rho / P;
+    Pb += Tb / (rho * R);
+    rb -= Tb * T * ir;
+    rb += bb * 0.5 / P;
+    Pb -= bb * beta / P;
+    qb[4] = gm1 * Pb;
+    rb -= gm1 * Pb * 0.5 * k;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ub[d] -= gm1 * Pb * rho * u[d];
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        qb[1 + d] = ub[d] * ir;
+        s += ub[d] * u[d];
+    }
+    qb[0] = rb - s * ir;
+}
+
+struct NodeFull {
+    double q[5];
+    double u[3];
+    double P, T, rho;
+};
+
+__device__ __forceinline__ void load_node(const double *q, long long nodes, long long g, double gm1,
+                                          double R, NodeFull &n) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) n.q[c] = q[c * nodes + g];
+    n.rho = n.q[0];
+    const double ir = 1.0 / n.rho;
+    n.u[0] = n.q[1] * ir;
+    n.u[1] = n.q[2] * ir;
+    n.u[2] = n.q[3] * ir;
+    n.P = gm1 * (n.q[4] - 0.5 * n.rho * (n.u[0] * n.u[0] + n.u[1] * n.u[1] + n.u[2] * n.u[2]));
+    n.T = n.P / (n.rho * R);
+}
+
+// ------------------------------------------------------------------------------------------
+// Pass 1: cotangents of the BR1 gradients, and the state-dependence part of the viscous flux.
+// ------------------------------------------------------------------------------------------
+template <int N, int EPW>
+__global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
+k_vjp_visc(const VjpArgs a) {
+    constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
+    __shared__ double s_buf[8 * NODES];
+    __shared__ double s_D[N2];
+    const int tid = threadIdx.x;
+    if (tid < N2) s_D[tid] = a.D[tid];
+    const int slot = tid / N3;
+    const int ln = tid - slot * N3;
+    const long long e = xcd_block(blockIdx.x, gridDim.x) * EPW + slot;
+    const bool active = (tid < NODES) && (e < a.K);
+    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+    const int idx[3] = {i1, i2, i3};
+    const int stride[3] = {1, N, N2};
+    const long long nodes = a.nodes;
+    const long long g = e * N3 + ln;
+    const double gm1 = a.gamma - 1.0;
+    const double isw = 1.0 / a.w_end;
+    const double mu = a.mu;
+    const double kap = a.mu * a.gamma * a.R / ((a.gamma - 1.0) * a.Pr);
+
+    NodeFull me;
+    double A[3][3];
+    double J = 1.0, rb[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        load_node(a.q, nodes, g, gm1, a.R, me);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[l][m] = a.metric[(3 * l + m) * nodes + g];
+        J = a.jac[g];
+        const double iJ = 1.0 / J;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rb[c] = a.gbar[(c + 1) * nodes + g] * iJ;
+    } else {
+        me.q[0] = 1.0; me.q[1] = me.q[2] = me.q[3] = 0.0; me.q[4] = 1.0;
+        me.rho = 1.0; me.u[0] = me.u[1] = me.u[2] = 0.0; me.P = 1.0; me.T = 1.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[l][m] = 0.0;
+    }
+    const double iJ = 1.0 / J;
+    const double iT = 1.0 / me.T;
+    const double w[4] = {me.u[0] * iT, me.u[1] * iT, me.u[2] * iT, -iT};
+    if (tid < NODES) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            s_buf[c * NODES + tid] = w[c];
+            s_buf[(4 + c) * NODES + tid] = rb[c];
+        }
+    }
+    __syncthreads();
+    double th[3][4], fhb[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) th[d][c] = fhb[d][c] = 0.0;
+        if (tid < NODES) {
+            const int il = idx[d];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const int pn = tid + (b - il) * stride[d];
+                const double dd = s_D[il * N + b];   // theta_d = D_d w
+                const double dt = s_D[b * N + il];   // fhat_d cotangent = D_d^T rbar
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    th[d][c] = fma(dd, s_buf[c * NODES + pn], th[d][c]);
+                    fhb[d][c] = fma(dt, s_buf[(4 + c) * NODES + pn], fhb[d][c]);
+                }
+            }
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int il = idx[d];
+            if (il != 0 && il != N - 1) continue;
+            const int side = (il == N - 1) ? 1 : 0;
+            const double s = side ? 1.0 : -1.0;
+            const long long nb = a.nbr[e * 6 + 2 * d + side];
+            if (nb < 0 || nb >= a.K) continue;
+            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
+            NodeFull o;
+            load_node(a.q, nodes, pg, gm1, a.R, o);
+            const double iTn = 1.0 / o.T;
+            const double wn[4] = {o.u[0] * iTn, o.u[1] * iTn, o.u[2] * iTn, -iTn};
+            const double iJn = 1.0 / a.jac[pg];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                th[d][c] = fma(0.5 * s * isw, wn[c] - w[c], th[d][c]);
+                // own SAT^V half and the neighbour's SAT^V at the partner node
+                const double rbn = a.gbar[(c + 1) * nodes + pg] * iJn;
+                fhb[d][c] = fma(-0.5 * s * isw, rb[c] + rbn, fhb[d][c]);
+            }
+        }
+    }
+    double gr[3][4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            gr[j][c] = (A[0][j] * th[0][c] + A[1][j] * th[1][c] + A[2][j] * th[2][c]) * iJ;
+    double Fb[3][4];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            Fb[m][c] = A[0][m] * fhb[0][c] + A[1][m] * fhb[1][c] + A[2][m] * fhb[2][c];
+    double gb[3][4], ub[3] = {0.0, 0.0, 0.0}, Tb = 0.0;
+    visc_flux_vjp(gr, me.u, me.T, mu, kap, Fb, gb, ub, Tb);
+    if (active) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                a.thb[(d * 4 + c) * nodes + g] =
+                    (A[d][0] * gb[0][c] + A[d][1] * gb[1][c] + A[d][2] * gb[2][c]) * iJ;
+        double qb[5];
+        prim_vjp(me.q, gm1, a.R, 0.0, ub, 0.0, 0.0, Tb, qb);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] = qb[c];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pass 2: everything else; adds to the partial qbar of pass 1 when VISC.
+// ------------------------------------------------------------------------------------------
+template <int N, int EPW, bool VISC>
+__global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
+k_vjp_main(const VjpArgs a) {
+    constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
+    constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6, F_K = 7;
+    constexpr int F_A = 8, F_RB = 11, F_MSG = 16;
+    __shared__ double s_buf[21 * NODES];
+    __shared__ double s_D[N2];
+    const int tid = threadIdx.x;
+    if (tid < N2) s_D[tid] = a.D[tid];
+    const int slot = tid / N3;
+    const int ln = tid - slot * N3;
+    const long long e = xcd_block(blockIdx.x, gridDim.x) * EPW + slot;
+    const bool active = (tid < NODES) && (e < a.K);
+    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+    const int idx[3] = {i1, i2, i3};
+    const int stride[3] = {1, N, N2};
+    const long long nodes = a.nodes;
+    const long long g = e * N3 + ln;
+    const double gm1 = a.gamma - 1.0;
+    const double w_end = a.w_end;
+    const double isw = 1.0 / w_end;
+
+    double q[5], A[3][3], J = 1.0, rb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q[c] = a.q[c * nodes + g];
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[l][m] = a.metric[(3 * l + m) * nodes + g];
+        J = a.jac[g];
+        const double iJ0 = 1.0 / J;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) rb[c] = a.gbar[c * nodes + g] * iJ0;
+    } else {
+        q[0] = 1.0; q[1] = q[2] = q[3] = 0.0; q[4] = 1.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) A[l][m] = 0.0;
+    }
+    Node me;
+    double Pme;
+    bool ok;
+    primitives(q, gm1, me, Pme, ok);
+    if (active && !ok) atomicOr(a.status, FLAG_NONPHYSICAL);
+    if (tid < NODES) {
+        s_buf[F_RHO * NODES + tid] = me.rho;
+        s_buf[F_U1 * NODES + tid] = me.u1;
+        s_buf[F_U2 * NODES + tid] = me.u2;
+        s_buf[F_U3 * NODES + tid] = me.u3;
+        s_buf[F_B * NODES + tid] = me.beta;
+        s_buf[F_LR * NODES + tid] = me.lrho;
+        s_buf[F_LB * NODES + tid] = me.lbeta;
+        s_buf[F_K * NODES + tid] = me.k;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s_buf[(F_RB + c) * NODES + tid] = rb[c];
+    }
+    // own accumulators: cotangents of rho, U, beta (and P, T below), plus direct qbar terms
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double Pb = 0.0, Tb = 0.0;
+    double qdir[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+    // ---- inviscid volume pairs ------------------------------------------------------------
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (tid < NODES) {
+            s_buf[(F_A + 0) * NODES + tid] = A[l][0];
+            s_buf[(F_A + 1) * NODES + tid] = A[l][1];
+            s_buf[(F_A + 2) * NODES + tid] = A[l][2];
+        }
+        __syncthreads();
+        const int il = idx[l];
+        const int st = stride[l];
+        auto pair = [&](int b, bool send) {
+            const int pn = tid + (b - il) * st;
+            Node o;
+            o.rho = s_buf[F_RHO * NODES + pn];
+            o.u1 = s_buf[F_U1 * NODES + pn];
+            o.u2 = s_buf[F_U2 * NODES + pn];
+            o.u3 = s_buf[F_U3 * NODES + pn];
+            o.beta = s_buf[F_B * NODES + pn];
+            o.lrho = s_buf[F_LR * NODES + pn];
+            o.lbeta = s_buf[F_LB * NODES + pn];
+            o.k = s_buf[F_K * NODES + pn];
+            const double n0 = A[l][0] + s_buf[(F_A + 0) * NODES + pn];
+            const double n1 = A[l][1] + s_buf[(F_A + 1) * NODES + pn];
+            const double n2 = A[l][2] + s_buf[(F_A + 2) * NODES + pn];
+            const double dab = s_D[il * N + b], dba = s_D[b * N + il];
+            double fb[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) fb[c] = -dab * rb[c] - dba * s_buf[(F_RB + c) * NODES + pn];
+            NodeBar ab, bb;
+            flux_n_vjp(me, o, n0, n1, n2, gm1, fb, ab, bb);
+            double ra[5];
+            reduce_bar(me, ab, ra);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[c] += ra[c];
+            if (send) {
+                double rbb[5];
+                reduce_bar(o, bb, rbb);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) s_buf[(F_MSG + c) * NODES + pn] = rbb[c];
+            }
+        };
+#pragma unroll
+        for (int r = 1; 2 * r < N; ++r) {
+            int b = il + r;
+            if (b >= N) b -= N;
+            if (tid < NODES) pair(b, true);
+            __syncthreads();
+            if (tid < NODES) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] += s_buf[(F_MSG + c) * NODES + tid];
+            }
+            __syncthreads();
+        }
+        if constexpr (N % 2 == 0) {
+            // both nodes of the pair evaluate it; each keeps its own cotangent
+            if (tid < NODES) {
+                int b = il + N / 2;
+                if (b >= N) b -= N;
+                pair(b, false);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- interface SAT and dissipation (own and neighbour view) ----------------------------
+    double wme[4] = {0.0, 0.0, 0.0, 0.0}, wb[4] = {0.0, 0.0, 0.0, 0.0};
+    const double Tme = 0.5 / (a.R * me.beta);
+    if (VISC) {
+        const double iT = 1.0 / Tme;
+        wme[0] = me.u1 * iT; wme[1] = me.u2 * iT; wme[2] = me.u3 * iT; wme[3] = -iT;
+    }
+    const double mu = a.mu;
+    const double kap = a.mu * a.gamma * a.R / ((a.gamma - 1.0) * a.Pr);
+    const double iJ = 1.0 / J;
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int il = idx[l];
+            if (il != 0 && il != N - 1) continue;
+            const int side = (il == N - 1) ? 1 : 0;
+            const double s = side ? 1.0 : -1.0;
+            const long long nb = a.nbr[e * 6 + 2 * l + side];
+            if (nb < 0 || nb >= a.K) continue;
+            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
+            double qn[5], rbn[5];
+            const double iJn = 1.0 / a.jac[pg];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                qn[c] = a.q[c * nodes + pg];
+                rbn[c] = a.gbar[c * nodes + pg] * iJn;
+            }
+            double An[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) An[m] = a.metric[(3 * l + m) * nodes + pg];
+            Node o;
+            double Pn;
+            bool okn;
+            primitives(qn, gm1, o, Pn, okn);
+            const double n0 = 0.5 * (A[l][0] + An[0]), n1 = 0.5 * (A[l][1] + An[1]),
+                         n2 = 0.5 * (A[l][2] + An[2]);
+            double fb[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) fb[c] = -s * isw * (rb[c] - rbn[c]);
+            NodeBar ab, bb;
+            flux_n_vjp(me, o, n0, n1, n2, gm1, fb, ab, bb);
+            double ra[5];
+            reduce_bar(me, ab, ra);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[c] += ra[c];
+            if (a.iface_diss) {
+                const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+                const double unm = me.u1 * n0 + me.u2 * n1 + me.u3 * n2;
+                const double cme = sqrt(a.gamma * Pme / me.rho);
+                const double li = fabs(unm) + cme * nn;
+                const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
+                const double lam = fmax(li, lo);
+                double t_own = 0.0, t_nb = 0.0;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    qdir[c] -= 0.5 * lam * isw * (rb[c] - rbn[c]);
+                    t_own += (q[c] - qn[c]) * rb[c];
+                    t_nb += (qn[c] - q[c]) * rbn[c];
+                }
+                // lambda depends on this node in the own view when li >= lo (ties go to the own
+                // side) and in the neighbour's view only when li > lo
+                double lb = 0.0;
+                if (li >= lo) lb -= 0.5 * isw * t_own;
+                if (li > lo) lb -= 0.5 * isw * t_nb;
+                if (lb != 0.0) {
+                    const double sg = unm >= 0.0 ? lb : -lb;
+                    acc[1] = fma(sg, n0, acc[1]);
+                    acc[2] = fma(sg, n1, acc[2]);
+                    acc[3] = fma(sg, n2, acc[3]);
+                    const double cb = lb * nn;
+                    Pb += cb * a.gamma / (2.0 * cme * me.rho);
+                    acc[0] -= cb * cme / (2.0 * me.rho);
+                }
+            }
+            if constexpr (VISC) {
+                if (a.eta != 0.0) {
+                    // interior penalty X = -(eta/(2 w_end)) [Phi_i(A_i dw/J_i) + Phi_nu(A_nu dw/J_nu)],
+                    // with cotangent rbar_i - rbar_nu (the neighbour's term is -X)
+                    const double iTn = 2.0 * a.R * o.beta;
+                    const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
+                    double dw[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dw[c] = wme[c] - wn[c];
+                    const double cf = -0.5 * a.eta * isw;
+                    double Fb_i[3][4], Fb_n[3][4], gi[3][4], gn[3][4];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const double xb = cf * (rb[c + 1] - rbn[c + 1]);
+                            Fb_i[m][c] = A[l][m] * xb;
+                            Fb_n[m][c] = An[m] * xb;
+                            gi[m][c] = A[l][m] * dw[c] * iJ;
+                            gn[m][c] = An[m] * dw[c] * iJn;
+                        }
+                    double gbi[3][4], gbn[3][4];
+                    double umv[3] = {me.u1, me.u2, me.u3};
+                    double unv[3] = {o.u1, o.u2, o.u3};
+                    double ubi[3] = {0.0, 0.0, 0.0}, ubn[3] = {0.0, 0.0, 0.0};
+                    double Tbn = 0.0;
+                    visc_flux_vjp(gi, umv, Tme, mu, kap, Fb_i, gbi, ubi, Tb);
+                    visc_flux_vjp(gn, unv, 1.0 / iTn, mu, kap, Fb_n, gbn, ubn, Tbn);
+                    acc[1] += ubi[0];
+                    acc[2] += ubi[1];
+                    acc[3] += ubi[2];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        double dwb = 0.0;
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            dwb += A[l][j] * gbi[j][c] * iJ + An[j] * gbn[j][c] * iJn;
+                        wb[c] += dwb;
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (VISC) {
+        // ---- transposed gradient operator D_a^T thetabar_a and its SAT -----------------------
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double thb_me[4] = {0.0, 0.0, 0.0, 0.0};
+            if (active) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) thb_me[c] = a.thb[(d * 4 + c) * nodes + g];
+            }
+            __syncthreads();
+            if (tid < NODES) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s_buf[c * NODES + tid] = thb_me[c];
+            }
+            __syncthreads();
+            if (tid < NODES) {
+                const int il = idx[d];
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const double dt = s_D[b * N + il];
+                    const int pn = tid + (b - il) * stride[d];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) wb[c] = fma(dt, s_buf[c * NODES + pn], wb[c]);
+                }
+            }
+            if (active) {
+                const int il = idx[d];
+                if (il == 0 || il == N - 1) {
+                    const int side = (il == N - 1) ? 1 : 0;
+                    const double s = side ? 1.0 : -1.0;
+                    const long long nb = a.nbr[e * 6 + 2 * d + side];
+                    if (nb >= 0 && nb < a.K) {
+                        const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            wb[c] = fma(-0.5 * s * isw, thb_me[c] + a.thb[(d * 4 + c) * nodes + pg], wb[c]);
+                    }
+                }
+            }
+        }
+        // w = (U/T, -1/T)
+        const double iT = 1.0 / Tme;
+        acc[1] = fma(wb[0], iT, acc[1]);
+        acc[2] = fma(wb[1], iT, acc[2]);
+        acc[3] = fma(wb[2], iT, acc[3]);
+        Tb += (-(wb[0] * me.u1 + wb[1] * me.u2 + wb[2] * me.u3) + wb[3]) * iT * iT;
+    }
+
+    if (active) {
+        double ub[3] = {acc[1], acc[2], acc[3]};
+        double qb[5];
+        prim_vjp(q, gm1, a.R, acc[0], ub, acc[4], Pb, Tb, qb);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            double v = qb[c] + qdir[c];
+            if (VISC) v += a.qbar[c * nodes + g];
+            a.qbar[c * nodes + g] = v;
+        }
+    }
+}
+
+template <int N, int EPW>
+int launch_vjp_n(const VjpArgs &a, hipStream_t s) {
+    constexpr int NT = NT_OF(EPW * N * N * N);
+    const long long blocks = (a.K + EPW - 1) / EPW;
+    if (a.mu != 0.0) {
+        hipLaunchKernelGGL((k_vjp_visc<N, EPW>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return -1;
+        hipLaunchKernelGGL((k_vjp_main<N, EPW, true>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_vjp_main<N, EPW, false>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace
+
+int launch_vjp(int p, const VjpArgs &a, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_vjp_n<2, 8>(a, s);
+        case 2: return launch_vjp_n<3, 2>(a, s);
+        case 3: return launch_vjp_n<4, 1>(a, s);
+        case 4: return launch_vjp_n<5, 1>(a, s);
+        case 5: return launch_vjp_n<6, 1>(a, s);
+        case 6: return launch_vjp_n<7, 1>(a, s);
+        case 7: return launch_vjp_n<8, 1>(a, s);
+        case 8: return launch_vjp_n<9, 1>(a, s);
+        default: return -1;
+    }
+}
+
+}  // namespace sbp
