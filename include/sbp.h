@@ -121,6 +121,22 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
 int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
                          void *ws, size_t ws_bytes, void *stream, float *kernel_ms);
 
+/* Autotuner: for each group of problems sharing degree, viscosity on/off and flux, times every
+ * schedule of the residual kernel (elements per workgroup; one block per element tile or a
+ * persistent grid) on these inputs, `reps` launches each after a warm-up, and keeps the fastest for
+ * later calls with the same problem array and workspace.  Waits for `stream`.  dqdt is scratch
+ * output.  chosen: optional host [n_prob] receiving the schedule index of each problem's group. */
+int sbp_autotune(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt, void *ws,
+                 size_t ws_bytes, void *stream, int32_t reps, int32_t *chosen);
+
+/* Number of residual schedules available for degree p (0 if p is out of range). */
+int sbp_schedule_count(int32_t p);
+
+/* Pins schedule `variant` (0 <= variant < sbp_schedule_count(p); 0 is the default) for the groups of
+ * degree p of this problem array and workspace, as sbp_autotune would.  Host call; no device work. */
+int sbp_set_schedule(const sbp_problem *probs, int32_t n_prob, void *ws, size_t ws_bytes, int32_t p,
+                     int32_t variant);
+
 /* Waits for `stream`, then reports and clears the workspace's sticky device flags:
  * *flags = 0 when every state seen since the last call was physical, else SBP_ERR_NONPHYSICAL's
  * bit 1.  Returns SBP_ERR_NONPHYSICAL in that case, SBP_OK otherwise. */

@@ -2,5 +2,5 @@
 Navier-Stokes equations (Rojas et al., arXiv 1911.10966): C-ABI library ``libsbp_hip.so`` plus a
 thin ctypes binding.  The library must be built (``python -m paper_1911_10966_amd.build``); there is
 no CPU fallback."""
-from .api import Problem, ProblemSet, SBPResidual, lgl_operator, metrics  # noqa: F401
+from .api import Problem, ProblemSet, SBPResidual, lgl_operator, metrics, schedule_count  # noqa: F401
 from ._lib import LIB_PATH, SBPError, lib  # noqa: F401

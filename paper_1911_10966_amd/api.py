@@ -27,6 +27,10 @@ def lgl_operator(p: int):
     return x, w, D.reshape(N, N)
 
 
+def schedule_count(p: int) -> int:
+    return int(lib().sbp_schedule_count(p))
+
+
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -127,6 +131,20 @@ class ProblemSet:
                                          self.ws_bytes, _stream(), ctypes.byref(ms)),
               "sbp_profile_residual")
         return float(ms.value)
+
+    def autotune(self, q: torch.Tensor, reps: int = 3):
+        """Times every residual schedule on these inputs and keeps the fastest per group; returns
+        the schedule index chosen for each problem."""
+        self._check_state(q, "q")
+        out = torch.empty_like(q)
+        chosen = (ctypes.c_int32 * self.n)()
+        check(lib().sbp_autotune(self._arr, self.n, _ptr(q), _ptr(out), _ptr(self.ws), self.ws_bytes,
+                                 _stream(), reps, chosen), "sbp_autotune")
+        return list(chosen)
+
+    def set_schedule(self, p: int, variant: int):
+        check(lib().sbp_set_schedule(self._arr, self.n, _ptr(self.ws), self.ws_bytes, p, variant),
+              "sbp_set_schedule")
 
     def rk_step(self, q: torch.Tensor, dt: torch.Tensor, n_steps: int = 1) -> torch.Tensor:
         """In-place classical RK4 steps; dt is a device float64 tensor with one entry per problem."""

@@ -192,60 +192,167 @@ int validate(const sbp_problem *probs, int32_t n_prob, void *ws, size_t ws_bytes
     return SBP_OK;
 }
 
-sbp::ResArgs res_args(const sbp_problem &pr, const double *q, double *out, char *ws, size_t trace_off) {
-    sbp::ResArgs a{};
-    const int N = pr.p + 1;
+// ------------------------------------------------------------------------------------------
+// Plans: problems grouped by (degree, viscous, flux), each group with a device table of its
+// problems, prefix sums of element tiles (per elements-per-workgroup option) and of nodes, and
+// the schedule variant chosen for it.  Cached per (problem array contents, workspace, device).
+// ------------------------------------------------------------------------------------------
+struct GroupPlan {
+    int p = 0;
+    bool visc = false;
+    int flux = 0;
+    std::vector<int> members;
+    sbp::ProbDev *d_probs = nullptr;
+    long long *d_node_start = nullptr;
+    long long total_nodes = 0;
+    std::map<int, long long *> d_block_start;  // by elements per workgroup
+    std::map<int, long long> total_blocks;
+    int variant = 0;
+};
+
+struct Plan {
+    std::vector<GroupPlan> groups;
+    int generation = 0;
+};
+
+std::mutex g_plan_mu;
+std::map<std::string, Plan *> g_plans;
+int g_generation = 0;
+
+std::string plan_key(const sbp_problem *probs, int n, const void *ws, int dev) {
+    std::string k(reinterpret_cast<const char *>(probs), sizeof(sbp_problem) * n);
+    k.append(reinterpret_cast<const char *>(&ws), sizeof(ws));
+    k.append(reinterpret_cast<const char *>(&dev), sizeof(dev));
+    return k;
+}
+
+template <typename T>
+T *to_device(const std::vector<T> &v) {
+    T *d = nullptr;
+    if (hipMalloc(&d, sizeof(T) * v.size()) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return d;
+}
+
+Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    const std::string key = plan_key(probs, n, ws, dev);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+    Plan *plan = new Plan();
+    std::vector<long long> off(n, 0);
+    long long acc = 0;
+    for (int b = 0; b < n; ++b) {
+        off[b] = acc;
+        acc += 5 * nodes_of(probs[b]);
+    }
+    for (int b = 0; b < n; ++b) {
+        const bool visc = probs[b].mu > 0.0;
+        GroupPlan *gp = nullptr;
+        for (auto &g : plan->groups)
+            if (g.p == probs[b].p && g.visc == visc && g.flux == probs[b].two_point) gp = &g;
+        if (!gp) {
+            plan->groups.emplace_back();
+            gp = &plan->groups.back();
+            gp->p = probs[b].p;
+            gp->visc = visc;
+            gp->flux = probs[b].two_point;
+        }
+        gp->members.push_back(b);
+    }
+    for (auto &g : plan->groups) {
+        std::vector<sbp::ProbDev> host;
+        std::vector<long long> ns(1, 0);
+        for (int b : g.members) {
+            const sbp_problem &pr = probs[b];
+            sbp::ProbDev d{};
+            d.metric = pr.metric;
+            d.jac = pr.jac;
+            d.nbr = pr.nbr;
+            d.trace = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.trace[b]) : nullptr;
+            d.thb = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.thb[b]) : nullptr;
+            d.K = pr.n_elem;
+            d.nodes = nodes_of(pr);
+            d.off = off[b];
+            d.gamma = pr.gamma;
+            d.R = pr.R;
+            d.mu = pr.mu;
+            d.Pr = pr.Pr;
+            d.eta = pr.eta;
+            d.w_end = host_op(pr.p).w[0];
+            d.iface_diss = pr.iface_diss;
+            d.two_point = pr.two_point;
+            d.dt_index = b;
+            host.push_back(d);
+            ns.push_back(ns.back() + d.nodes);
+        }
+        g.d_probs = to_device(host);
+        g.d_node_start = to_device(ns);
+        g.total_nodes = ns.back();
+        if (!g.d_probs || !g.d_node_start) return nullptr;
+        for (int v = 0; v < sbp::schedule_count(g.p); ++v) {
+            const int epw = sbp::schedule_of(g.p, v).epw;
+            if (g.d_block_start.count(epw)) continue;
+            std::vector<long long> bs(1, 0);
+            for (int b : g.members) bs.push_back(bs.back() + (probs[b].n_elem + epw - 1) / epw);
+            g.d_block_start[epw] = to_device(bs);
+            g.total_blocks[epw] = bs.back();
+            if (!g.d_block_start[epw]) return nullptr;
+        }
+    }
+    plan->generation = ++g_generation;
+    g_plans[key] = plan;
+    return plan;
+}
+
+sbp::GroupArgs group_args(const GroupPlan &g, int variant, const double *q, double *out, char *ws) {
+    sbp::GroupArgs a{};
+    const int epw = sbp::schedule_of(g.p, variant).epw;
+    a.probs = g.d_probs;
+    a.block_start = g.d_block_start.at(epw);
+    a.node_start = g.d_node_start;
+    a.n = (int)g.members.size();
+    a.total_blocks = g.total_blocks.at(epw);
+    a.total_nodes = g.total_nodes;
     a.q = q;
     a.out = out;
-    a.metric = pr.metric;
-    a.jac = pr.jac;
-    a.nbr = pr.nbr;
-    a.trace = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + trace_off) : nullptr;
     a.status = reinterpret_cast<int *>(ws);
-    a.D = device_D(pr.p);
-    a.K = pr.n_elem;
-    a.nodes = pr.n_elem * (long long)N * N * N;
-    a.gamma = pr.gamma;
-    a.R = pr.R;
-    a.mu = pr.mu;
-    a.Pr = pr.Pr;
-    a.eta = pr.eta;
-    a.w_end = host_op(pr.p).w[0];
-    a.iface_diss = pr.iface_diss;
-    a.two_point = pr.two_point;
+    a.D = device_D(g.p);
     return a;
 }
 
-int residual_all(const sbp_problem *probs, int n, const double *q, double *out, char *ws,
-                 const Layout &L, hipStream_t s, bool fixup = true) {
-    size_t off = 0;
-    for (int b = 0; b < n; ++b) {
-        sbp::ResArgs a = res_args(probs[b], q + off, out + off, ws, L.trace[b]);
-        if (a.D == nullptr) return SBP_ERR_HIP;
-        if (sbp::launch_residual(probs[b].p, a, s, fixup) != 0) return SBP_ERR_HIP;
-        off += 5 * (size_t)nodes_of(probs[b]);
+int residual_group(const GroupPlan &g, const double *q, double *out, char *ws, hipStream_t s,
+                   bool fixup, int variant) {
+    sbp::GroupArgs a = group_args(g, variant, q, out, ws);
+    if (a.D == nullptr) return SBP_ERR_HIP;
+    return sbp::launch_group_residual(g.p, g.visc, g.flux, variant, a, s, fixup) == 0 ? SBP_OK
+                                                                                     : SBP_ERR_HIP;
+}
+
+int residual_all(Plan *plan, const double *q, double *out, char *ws, hipStream_t s) {
+    for (const auto &g : plan->groups) {
+        const int rc = residual_group(g, q, out, ws, s, true, g.variant);
+        if (rc != SBP_OK) return rc;
     }
     return SBP_OK;
 }
 
-// One RK4 step = four (residual, stage update) pairs.
-int rk_step_launches(const sbp_problem *probs, int n, double *q, const double *dt, char *ws,
-                     const Layout &L, hipStream_t s) {
+// One RK4 step of one group = four (residual, stage update) pairs.
+int rk_step_group(const GroupPlan &g, double *q, const double *dt, char *ws, const Layout &L,
+                  hipStream_t s) {
+    const size_t sb = align_up(sizeof(double) * L.total_state);
     double *acc = reinterpret_cast<double *>(ws + L.rk);
-    double *qs = reinterpret_cast<double *>(ws + L.rk + align_up(sizeof(double) * L.total_state));
-    double *k = reinterpret_cast<double *>(ws + L.rk + 2 * align_up(sizeof(double) * L.total_state));
+    double *qs = reinterpret_cast<double *>(ws + L.rk + sb);
+    double *k = reinterpret_cast<double *>(ws + L.rk + 2 * sb);
     for (int stage = 0; stage < 4; ++stage) {
         const double *src = stage == 0 ? q : qs;
-        const int rc = residual_all(probs, n, src, k, ws, L, s, false);
+        int rc = residual_group(g, src, k, ws, s, false, g.variant);
         if (rc != SBP_OK) return rc;
-        size_t off = 0;
-        for (int b = 0; b < n; ++b) {
-            const long long cnt = 5 * nodes_of(probs[b]);
-            sbp::ResArgs a = res_args(probs[b], src + off, k + off, ws, L.trace[b]);
-            sbp::RkArgs r{q + off, acc + off, qs + off, k + off, dt + b, cnt, stage};
-            if (sbp::launch_rk_fixup_stage(probs[b].p, a, r, s) != 0) return SBP_ERR_HIP;
-            off += cnt;
-        }
+        sbp::GroupArgs a = group_args(g, g.variant, src, k, ws);
+        sbp::RkGroupArgs r{q, acc, qs, k, dt, stage};
+        if (sbp::launch_group_rk_stage(g.p, g.visc, a, r, s) != 0) return SBP_ERR_HIP;
     }
     return SBP_OK;
 }
@@ -253,9 +360,10 @@ int rk_step_launches(const sbp_problem *probs, int n, double *q, const double *d
 struct GraphKey {
     std::string probs;
     const void *q, *dt, *ws;
-    int dev;
+    int dev, generation;
     bool operator<(const GraphKey &o) const {
         if (dev != o.dev) return dev < o.dev;
+        if (generation != o.generation) return generation < o.generation;
         if (q != o.q) return q < o.q;
         if (dt != o.dt) return dt < o.dt;
         if (ws != o.ws) return ws < o.ws;
@@ -265,6 +373,43 @@ struct GraphKey {
 
 std::mutex g_graph_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+// Records one RK4 step of every group into a graph; groups are independent branches.
+int record_rk_graph(Plan *plan, double *q, const double *dt, char *ws, const Layout &L,
+                    hipGraphExec_t *exec) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SBP_ERR_HIP;
+    std::vector<hipStream_t> br(plan->groups.size(), nullptr);
+    std::vector<hipEvent_t> ev(plan->groups.size() + 1, nullptr);
+    int rc = SBP_OK;
+    for (size_t i = 0; i < br.size() && rc == SBP_OK; ++i)
+        if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) rc = SBP_ERR_HIP;
+    for (size_t i = 0; i < ev.size() && rc == SBP_OK; ++i)
+        if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) rc = SBP_ERR_HIP;
+    hipGraph_t graph = nullptr;
+    if (rc == SBP_OK && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        hipEventRecord(ev.back(), cap);
+        for (size_t i = 0; i < br.size() && rc == SBP_OK; ++i) {
+            hipStreamWaitEvent(br[i], ev.back(), 0);
+            rc = rk_step_group(plan->groups[i], q, dt, ws, L, br[i]);
+            hipEventRecord(ev[i], br[i]);
+            hipStreamWaitEvent(cap, ev[i], 0);
+        }
+        const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        if (rc == SBP_OK && (ec != hipSuccess || graph == nullptr)) rc = SBP_ERR_HIP;
+    } else if (rc == SBP_OK) {
+        rc = SBP_ERR_HIP;
+    }
+    if (rc == SBP_OK && hipGraphInstantiate(exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = SBP_ERR_HIP;
+    if (graph) hipGraphDestroy(graph);
+    for (auto e : ev)
+        if (e) hipEventDestroy(e);
+    for (auto b : br)
+        if (b) hipStreamDestroy(b);
+    hipStreamDestroy(cap);
+    return rc;
+}
 
 }  // namespace
 
@@ -318,7 +463,9 @@ int sbp_residual(const sbp_problem *probs, int32_t n_prob, const double *q, doub
     int rc = validate(probs, n_prob, ws, ws_bytes, L);
     if (rc != SBP_OK) return rc;
     if (!aligned8(q) || !aligned8(dqdt) || q == dqdt) return SBP_ERR_ARG;
-    return residual_all(probs, n_prob, q, dqdt, static_cast<char *>(ws), L, (hipStream_t)stream);
+    Plan *plan = get_plan(probs, n_prob, static_cast<char *>(ws), L);
+    if (!plan) return SBP_ERR_HIP;
+    return residual_all(plan, q, dqdt, static_cast<char *>(ws), (hipStream_t)stream);
 }
 
 int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const double *dt,
@@ -331,11 +478,13 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SBP_ERR_HIP;
-    // make sure the operator tables exist before capture (no allocation inside a capture)
+    // operator tables and plan exist before capture (no allocation inside a capture)
     for (int b = 0; b < n_prob; ++b)
         if (!device_D(probs[b].p)) return SBP_ERR_HIP;
+    Plan *plan = get_plan(probs, n_prob, static_cast<char *>(ws), L);
+    if (!plan) return SBP_ERR_HIP;
     GraphKey key{std::string(reinterpret_cast<const char *>(probs), sizeof(sbp_problem) * n_prob),
-                 q, dt, ws, dev};
+                 q, dt, ws, dev, plan->generation};
     hipGraphExec_t exec = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -343,23 +492,8 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
         if (it != g_graphs.end()) exec = it->second;
     }
     if (exec == nullptr) {
-        hipStream_t cap;
-        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SBP_ERR_HIP;
-        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            hipStreamDestroy(cap);
-            return SBP_ERR_HIP;
-        }
-        rc = rk_step_launches(probs, n_prob, q, dt, static_cast<char *>(ws), L, cap);
-        hipGraph_t graph = nullptr;
-        const hipError_t ec = hipStreamEndCapture(cap, &graph);
-        hipStreamDestroy(cap);
-        if (rc != SBP_OK || ec != hipSuccess || graph == nullptr) {
-            if (graph) hipGraphDestroy(graph);
-            return rc != SBP_OK ? rc : SBP_ERR_HIP;
-        }
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (ei != hipSuccess) return SBP_ERR_HIP;
+        rc = record_rk_graph(plan, q, dt, static_cast<char *>(ws), L, &exec);
+        if (rc != SBP_OK) return rc;
         std::lock_guard<std::mutex> lk(g_graph_mu);
         g_graphs[key] = exec;
     }
@@ -420,14 +554,83 @@ int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double 
         if (hipEventCreate(&tm.begin) != hipSuccess || hipEventCreate(&tm.end) != hipSuccess)
             return SBP_ERR_HIP;
     }
+    Plan *plan = get_plan(probs, n_prob, static_cast<char *>(ws), L);
+    if (!plan) return SBP_ERR_HIP;
     tm.enabled = true;
-    rc = residual_all(probs, n_prob, q, dqdt, static_cast<char *>(ws), L, (hipStream_t)stream);
+    rc = residual_group(plan->groups[0], q, dqdt, static_cast<char *>(ws), (hipStream_t)stream, true,
+                        plan->groups[0].variant);
     tm.enabled = false;
     if (rc != SBP_OK) return rc;
     if (hipEventSynchronize(tm.end) != hipSuccess) return SBP_ERR_HIP;
     if (hipEventElapsedTime(kernel_ms, tm.begin, tm.end) != hipSuccess) return SBP_ERR_HIP;
     return SBP_OK;
 }
+
+int sbp_autotune(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt, void *ws,
+                 size_t ws_bytes, void *stream, int32_t reps, int32_t *chosen) {
+    Layout L;
+    int rc = validate(probs, n_prob, ws, ws_bytes, L);
+    if (rc != SBP_OK) return rc;
+    if (!aligned8(q) || !aligned8(dqdt) || q == dqdt || reps < 1) return SBP_ERR_ARG;
+    Plan *plan = get_plan(probs, n_prob, static_cast<char *>(ws), L);
+    if (!plan) return SBP_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SBP_ERR_HIP;
+    for (auto &g : plan->groups) {
+        const int nv = g.flux == 0 ? sbp::schedule_count(g.p) : 1;
+        float best = 0.0f;
+        int best_v = 0;
+        for (int v = 0; v < nv; ++v) {
+            rc = residual_group(g, q, dqdt, static_cast<char *>(ws), s, false, v);  // warm-up
+            if (rc != SBP_OK) break;
+            hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == SBP_OK; ++r)
+                rc = residual_group(g, q, dqdt, static_cast<char *>(ws), s, false, v);
+            hipEventRecord(e1, s);
+            if (rc != SBP_OK || hipEventSynchronize(e1) != hipSuccess) { rc = SBP_ERR_HIP; break; }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (v == 0 || ms < best) { best = ms; best_v = v; }
+        }
+        if (rc != SBP_OK) break;
+        g.variant = best_v;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != SBP_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        plan->generation = ++g_generation;  // graphs recorded with the old schedules are not reused
+    }
+    if (chosen) {
+        for (int b = 0; b < n_prob; ++b) chosen[b] = 0;
+        for (const auto &g : plan->groups)
+            for (int b : g.members) chosen[b] = g.variant;
+    }
+    return SBP_OK;
+}
+
+int sbp_set_schedule(const sbp_problem *probs, int32_t n_prob, void *ws, size_t ws_bytes, int32_t p,
+                     int32_t variant) {
+    Layout L;
+    int rc = validate(probs, n_prob, ws, ws_bytes, L);
+    if (rc != SBP_OK) return rc;
+    if (p < 1 || p > SBP_MAX_P) return SBP_ERR_DEGREE;
+    if (variant < 0 || variant >= sbp::schedule_count(p)) return SBP_ERR_ARG;
+    Plan *plan = get_plan(probs, n_prob, static_cast<char *>(ws), L);
+    if (!plan) return SBP_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto &g : plan->groups)
+        if (g.p == p) {
+            if (g.flux != SBP_FLUX_CHANDRASHEKAR && variant != 0) return SBP_ERR_ARG;
+            g.variant = variant;
+        }
+    plan->generation = ++g_generation;
+    return SBP_OK;
+}
+
+int sbp_schedule_count(int32_t p) { return (p < 1 || p > SBP_MAX_P) ? 0 : sbp::schedule_count(p); }
 
 int sbp_status(void *ws, void *stream, int32_t *flags) {
     if (ws == nullptr || flags == nullptr) return SBP_ERR_ARG;

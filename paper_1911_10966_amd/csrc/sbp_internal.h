@@ -27,6 +27,60 @@ struct ResArgs {
     int two_point;
 };
 
+// Static per-problem data of a group launch (device table entry).  `off` is the offset, in
+// doubles, of the problem's component-0 block in the concatenated state arrays.
+struct ProbDev {
+    const double *metric;
+    const double *jac;
+    const int32_t *nbr;
+    double *trace;
+    double *thb;
+    long long K;
+    long long nodes;
+    long long off;
+    double gamma, R, mu, Pr, eta;
+    double w_end;
+    int iface_diss;
+    int two_point;
+    int dt_index;
+    int pad;
+};
+
+// One launch over all problems of a group (same degree, viscosity on/off and flux).
+struct GroupArgs {
+    const ProbDev *probs;          // device [n]
+    const long long *block_start;  // device [n+1]: prefix sums of element tiles per problem
+    const long long *node_start;   // device [n+1]: prefix sums of nodes per problem
+    int n;
+    long long total_blocks;
+    long long total_nodes;
+    const double *q;               // base of the concatenated input state
+    double *out;                   // base of the concatenated output
+    int *status;
+    const double *D;
+};
+
+// RK4 stage update over a group: base pointers of the concatenated buffers.
+struct RkGroupArgs {
+    double *q;
+    double *acc;
+    double *qs;
+    const double *k;
+    const double *dt;              // device [n_prob of the whole set], indexed by ProbDev::dt_index
+    int stage;
+};
+
+// Schedules of the residual kernel: elements per workgroup and whether the grid is persistent.
+struct Schedule {
+    int epw;
+    int persistent;
+};
+int schedule_count(int p);
+Schedule schedule_of(int p, int variant);
+int launch_group_residual(int p, bool visc, int flux, int variant, const GroupArgs &g, hipStream_t s,
+                          bool fixup);
+int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArgs &r, hipStream_t s);
+
 // RK4 stage update, see launch_rk_stage.
 struct RkArgs {
     double *q;
@@ -38,10 +92,6 @@ struct RkArgs {
     int stage;
 };
 
-// Main residual kernel; with fixup the neighbour half of SAT^V is added by a second kernel,
-// without it the caller must apply it (launch_rk_fixup_stage does, for RK stages).
-int launch_residual(int p, const ResArgs &a, hipStream_t s, bool fixup = true);
-int launch_rk_fixup_stage(int p, const ResArgs &a, const RkArgs &r, hipStream_t s);
 
 // Optional event timing of the main residual kernel (see sbp_profile in the C ABI).
 struct KernelTimer {

@@ -12,20 +12,18 @@
 namespace sbp {
 namespace {
 
+// One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
 template <int N, int EPW, bool VISC, int FLUX>
-__global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
-k_residual(const ResArgs a) {
+__device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
+                                              const double *s_D) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
     constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6, F_K = 7;
     constexpr int F_A = 8, F_MSG = 11;
-    __shared__ double s_buf[16 * NODES];
-    __shared__ double s_D[N2];
 
     const int tid = threadIdx.x;
-    if (tid < N2) s_D[tid] = a.D[tid];
     const int slot = tid / N3;
     const int ln = tid - slot * N3;
-    const long long e = xcd_block(blockIdx.x, gridDim.x) * EPW + slot;
+    const long long e = ebase + slot;
     const bool active = (tid < NODES) && (e < a.K);
     const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
     const int idx[3] = {i1, i2, i3};
@@ -336,18 +334,76 @@ k_residual(const ResArgs a) {
     }
 }
 
-// Adds the neighbour half of SAT^V, (s/(2 w_end)) fhat_l,nu / J, at face nodes.
+__device__ __forceinline__ int find_problem(const long long *start, int n, long long v) {
+    int lo = 0, hi = n;  // start[lo] <= v < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDev &P, double *out) {
+    ResArgs a;
+    a.q = g.q + P.off;
+    a.out = out + P.off;
+    a.metric = P.metric;
+    a.jac = P.jac;
+    a.nbr = P.nbr;
+    a.trace = P.trace;
+    a.status = g.status;
+    a.D = g.D;
+    a.K = P.K;
+    a.nodes = P.nodes;
+    a.gamma = P.gamma;
+    a.R = P.R;
+    a.mu = P.mu;
+    a.Pr = P.Pr;
+    a.eta = P.eta;
+    a.w_end = P.w_end;
+    a.iface_diss = P.iface_diss;
+    a.two_point = P.two_point;
+    return a;
+}
+
+// Residual over a group of problems.  Non-persistent: one block per element tile.  Persistent:
+// a grid sized to the resident capacity walks the tiles (the grid is a multiple of the XCD count,
+// so the XCD-contiguous remap of tile indices still holds).
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST>
+__global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
+k_residual(const GroupArgs g) {
+    constexpr int N2 = N * N, NODES = EPW * N * N * N;
+    __shared__ double s_buf[16 * NODES];
+    __shared__ double s_D[N2];
+    if (threadIdx.x < N2) s_D[threadIdx.x] = g.D[threadIdx.x];
+    if constexpr (!PERSIST) {
+        const long long vb = xcd_block(blockIdx.x, gridDim.x);
+        const int b = find_problem(g.block_start, g.n, vb);
+        const ResArgs a = problem_view(g, g.probs[b], g.out);
+        residual_tile<N, EPW, VISC, FLUX>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+    } else {
+        for (long long it = blockIdx.x; it < g.total_blocks; it += gridDim.x) {
+            const long long vb = xcd_block(it, g.total_blocks);
+            const int b = find_problem(g.block_start, g.n, vb);
+            const ResArgs a = problem_view(g, g.probs[b], g.out);
+            residual_tile<N, EPW, VISC, FLUX>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+            __syncthreads();
+        }
+    }
+}
+
+// Neighbour half of SAT^V, (s/(2 w_end)) fhat_l,nu, for node gl of a problem.
 template <int N>
-__global__ void __launch_bounds__(256) k_visc_fixup(const ResArgs a) {
+__device__ __forceinline__ bool visc_fixup_add(const ResArgs &a, long long gl, double add[4]) {
     constexpr int N2 = N * N, N3 = N * N * N;
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.nodes) return;
-    const long long e = g / N3;
-    const int ln = (int)(g - e * N3);
+    const long long e = gl / N3;
+    const int ln = (int)(gl - e * N3);
     const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
     const int idx[3] = {i1, i2, i3};
     bool any = false;
-    double add[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) add[c] = 0.0;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const int il = idx[l];
@@ -363,53 +419,47 @@ __global__ void __launch_bounds__(256) k_visc_fixup(const ResArgs a) {
         for (int c = 0; c < 4; ++c) add[c] = fma(cf, tr[c * N2], add[c]);
         any = true;
     }
-    if (!any) return;
-    const double iJ = 1.0 / a.jac[g];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) a.out[(c + 1) * a.nodes + g] += add[c] * iJ;
+    return any;
 }
 
-// RK4 stage update fused with the neighbour half of SAT^V (viscous problems): thread per node.
+template <int N>
+__global__ void __launch_bounds__(256) k_group_fixup(const GroupArgs g) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.total_nodes) return;
+    const int b = find_problem(g.node_start, g.n, v);
+    const ResArgs a = problem_view(g, g.probs[b], g.out);
+    const long long gl = v - g.node_start[b];
+    double add[4];
+    if (!visc_fixup_add<N>(a, gl, add)) return;
+    const double iJ = 1.0 / a.jac[gl];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.out[(c + 1) * a.nodes + gl] += add[c] * iJ;
+}
+
+// RK4 stage update (and, for viscous problems, the neighbour half of SAT^V) over a group.
 template <int N, bool VISC>
-__global__ void __launch_bounds__(256) k_rk_fixup_stage(const ResArgs a, const RkArgs r) {
-    constexpr int N2 = N * N, N3 = N * N * N;
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.nodes) return;
+__global__ void __launch_bounds__(256) k_group_rk_stage(const GroupArgs g, const RkGroupArgs r) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.total_nodes) return;
+    const int b = find_problem(g.node_start, g.n, v);
+    const ProbDev &P = g.probs[b];
+    const ResArgs a = problem_view(g, P, const_cast<double *>(r.k));
+    const long long gl = v - g.node_start[b];
     double kk[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) kk[c] = r.k[c * a.nodes + g];
+    for (int c = 0; c < 5; ++c) kk[c] = a.out[c * a.nodes + gl];
     if constexpr (VISC) {
-        const long long e = g / N3;
-        const int ln = (int)(g - e * N3);
-        const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
-        const int idx[3] = {i1, i2, i3};
-        bool any = false;
-        double add[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int il = idx[l];
-            if (il != 0 && il != N - 1) continue;
-            const int side = (il == N - 1) ? 1 : 0;
-            const double s = side ? 1.0 : -1.0;
-            const long long nb = a.nbr[e * 6 + 2 * l + side];
-            if (nb < 0 || nb >= a.K) continue;
-            const int t = tangential_index<N>(l, i1, i2, i3);
-            const double *tr = a.trace + ((nb * 6 + 2 * l + (1 - side)) * 4) * N2 + t;
-            const double cf = 0.5 * s / a.w_end;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) add[c] = fma(cf, tr[c * N2], add[c]);
-            any = true;
-        }
-        if (any) {
-            const double iJ = 1.0 / a.jac[g];
+        double add[4];
+        if (visc_fixup_add<N>(a, gl, add)) {
+            const double iJ = 1.0 / a.jac[gl];
 #pragma unroll
             for (int c = 0; c < 4; ++c) kk[c + 1] = fma(add[c], iJ, kk[c + 1]);
         }
     }
-    const double dt = *r.dt;
+    const double dt = r.dt[P.dt_index];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        const long long i = c * a.nodes + g;
+        const long long i = P.off + c * a.nodes + gl;
         const double q = r.q[i];
         switch (r.stage) {
             case 0:
@@ -519,77 +569,177 @@ k_metrics(const double *x, double *metric, double *jac, const double *D, long lo
     }
 }
 
-template <int N, int EPW, bool VISC, int FLUX>
-int launch_res_t(const ResArgs &a, hipStream_t s, bool fixup) {
+// ---- launchers ---------------------------------------------------------------------------
+// Schedules per degree: {elements per workgroup, persistent grid}.  Entry 0 is the default.
+constexpr Schedule kSched2[] = {{8, 0}, {16, 0}, {8, 1}, {16, 1}};
+constexpr Schedule kSched3[] = {{2, 0}, {7, 0}, {2, 1}, {7, 1}};
+constexpr Schedule kSched4[] = {{1, 0}, {2, 0}, {4, 0}, {1, 1}, {2, 1}};
+constexpr Schedule kSched5[] = {{1, 0}, {2, 0}, {1, 1}, {2, 1}};
+constexpr Schedule kSchedBig[] = {{1, 0}, {1, 1}};
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST>
+int launch_res_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
-    const long long blocks = (a.K + EPW - 1) / EPW;
+    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST>;
+    long long grid = g.total_blocks;
+    if (PERSIST) {
+        static int per_cu = 0;
+        if (per_cu == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess ||
+                per_cu <= 0)
+                per_cu = 1;
+        }
+        long long cap = (long long)per_cu * device_cus();
+        cap = (cap / 8) * 8;
+        if (cap < 8) cap = 8;
+        if (grid > cap) grid = cap;
+    }
     KernelTimer &tm = residual_timer();
     if (tm.enabled) hipEventRecord(tm.begin, s);
-    hipLaunchKernelGGL((k_residual<N, EPW, VISC, FLUX>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, g);
     if (hipGetLastError() != hipSuccess) return -1;
     if (tm.enabled) hipEventRecord(tm.end, s);
-    if (VISC && fixup) {
-        const long long nb = (a.nodes + 255) / 256;
-        hipLaunchKernelGGL((k_visc_fixup<N>), dim3((unsigned)nb), dim3(256), 0, s, a);
-        if (hipGetLastError() != hipSuccess) return -1;
-    }
     return 0;
 }
 
-template <int N, int EPW>
-int launch_res_n(const ResArgs &a, hipStream_t s, bool fx) {
-    const bool visc = a.mu != 0.0;
-    switch (a.two_point) {
-        case 0: return visc ? launch_res_t<N, EPW, true, 0>(a, s, fx) : launch_res_t<N, EPW, false, 0>(a, s, fx);
-        case 1: return visc ? launch_res_t<N, EPW, true, 1>(a, s, fx) : launch_res_t<N, EPW, false, 1>(a, s, fx);
-        case 2: return visc ? launch_res_t<N, EPW, true, 2>(a, s, fx) : launch_res_t<N, EPW, false, 2>(a, s, fx);
+// Chandrashekar flux: every schedule; other fluxes: the default schedule only.
+template <int N, int EPW, bool PERSIST>
+int launch_res_e(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
+    if (flux == 0)
+        return visc ? launch_res_k<N, EPW, true, 0, PERSIST>(g, s)
+                    : launch_res_k<N, EPW, false, 0, PERSIST>(g, s);
+    if (PERSIST) return -1;
+    switch (flux) {
+        case 1: return visc ? launch_res_k<N, EPW, true, 1, false>(g, s) : launch_res_k<N, EPW, false, 1, false>(g, s);
+        case 2: return visc ? launch_res_k<N, EPW, true, 2, false>(g, s) : launch_res_k<N, EPW, false, 2, false>(g, s);
         default: return -1;
     }
 }
 
+template <int N, int EPW, bool PERSIST>
+int launch_res_e0(bool visc, const GroupArgs &g, hipStream_t s) {
+    return visc ? launch_res_k<N, EPW, true, 0, PERSIST>(g, s) : launch_res_k<N, EPW, false, 0, PERSIST>(g, s);
+}
+
 template <int N>
-int launch_rkfs_n(const ResArgs &a, const RkArgs &r, hipStream_t s) {
-    const long long nb = (a.nodes + 255) / 256;
-    if (a.mu != 0.0)
-        hipLaunchKernelGGL((k_rk_fixup_stage<N, true>), dim3((unsigned)nb), dim3(256), 0, s, a, r);
-    else
-        hipLaunchKernelGGL((k_rk_fixup_stage<N, false>), dim3((unsigned)nb), dim3(256), 0, s, a, r);
+int launch_fixup(const GroupArgs &g, hipStream_t s) {
+    const long long nb = (g.total_nodes + 255) / 256;
+    hipLaunchKernelGGL((k_group_fixup<N>), dim3((unsigned)nb), dim3(256), 0, s, g);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+int launch_rkg(bool visc, const GroupArgs &g, const RkGroupArgs &r, hipStream_t s) {
+    const long long nb = (g.total_nodes + 255) / 256;
+    if (visc) hipLaunchKernelGGL((k_group_rk_stage<N, true>), dim3((unsigned)nb), dim3(256), 0, s, g, r);
+    else hipLaunchKernelGGL((k_group_rk_stage<N, false>), dim3((unsigned)nb), dim3(256), 0, s, g, r);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
 
+int schedule_count(int p) {
+    switch (p) {
+        case 1: return (int)(sizeof(kSched2) / sizeof(Schedule));
+        case 2: return (int)(sizeof(kSched3) / sizeof(Schedule));
+        case 3: return (int)(sizeof(kSched4) / sizeof(Schedule));
+        case 4: return (int)(sizeof(kSched5) / sizeof(Schedule));
+        case 5: case 6: case 7: case 8: return (int)(sizeof(kSchedBig) / sizeof(Schedule));
+        default: return 0;
+    }
+}
+
+Schedule schedule_of(int p, int v) {
+    switch (p) {
+        case 1: return kSched2[v];
+        case 2: return kSched3[v];
+        case 3: return kSched4[v];
+        case 4: return kSched5[v];
+        default: return kSchedBig[v];
+    }
+}
+
+int launch_group_residual(int p, bool visc, int flux, int variant, const GroupArgs &g, hipStream_t s,
+                          bool fixup) {
+    if (variant < 0 || variant >= schedule_count(p)) return -1;
+    if (flux != 0 && variant != 0) return -1;
+    const Schedule sc = schedule_of(p, variant);
+    int rc = -1;
+    const bool P1 = sc.persistent != 0;
+    if (flux == 0) {
+#define SBP_CASE(NN, EE)                                                                \
+    if (sc.epw == EE) rc = P1 ? launch_res_e0<NN, EE, true>(visc, g, s)                 \
+                              : launch_res_e0<NN, EE, false>(visc, g, s);
+        switch (p) {
+            case 1: SBP_CASE(2, 8) SBP_CASE(2, 16) break;
+            case 2: SBP_CASE(3, 2) SBP_CASE(3, 7) break;
+            case 3: SBP_CASE(4, 1) SBP_CASE(4, 2) SBP_CASE(4, 4) break;
+            case 4: SBP_CASE(5, 1) SBP_CASE(5, 2) break;
+            case 5: SBP_CASE(6, 1) break;
+            case 6: SBP_CASE(7, 1) break;
+            case 7: SBP_CASE(8, 1) break;
+            case 8: SBP_CASE(9, 1) break;
+            default: return -1;
+        }
+#undef SBP_CASE
+    } else {
+        switch (p) {
+            case 1: rc = launch_res_e<2, 8, false>(visc, flux, g, s); break;
+            case 2: rc = launch_res_e<3, 2, false>(visc, flux, g, s); break;
+            case 3: rc = launch_res_e<4, 1, false>(visc, flux, g, s); break;
+            case 4: rc = launch_res_e<5, 1, false>(visc, flux, g, s); break;
+            case 5: rc = launch_res_e<6, 1, false>(visc, flux, g, s); break;
+            case 6: rc = launch_res_e<7, 1, false>(visc, flux, g, s); break;
+            case 7: rc = launch_res_e<8, 1, false>(visc, flux, g, s); break;
+            case 8: rc = launch_res_e<9, 1, false>(visc, flux, g, s); break;
+            default: return -1;
+        }
+    }
+    if (rc != 0) return rc;
+    if (visc && fixup) {
+        switch (p) {
+            case 1: return launch_fixup<2>(g, s);
+            case 2: return launch_fixup<3>(g, s);
+            case 3: return launch_fixup<4>(g, s);
+            case 4: return launch_fixup<5>(g, s);
+            case 5: return launch_fixup<6>(g, s);
+            case 6: return launch_fixup<7>(g, s);
+            case 7: return launch_fixup<8>(g, s);
+            case 8: return launch_fixup<9>(g, s);
+            default: return -1;
+        }
+    }
+    return 0;
+}
+
+int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArgs &r, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_rkg<2>(visc, g, r, s);
+        case 2: return launch_rkg<3>(visc, g, r, s);
+        case 3: return launch_rkg<4>(visc, g, r, s);
+        case 4: return launch_rkg<5>(visc, g, r, s);
+        case 5: return launch_rkg<6>(visc, g, r, s);
+        case 6: return launch_rkg<7>(visc, g, r, s);
+        case 7: return launch_rkg<8>(visc, g, r, s);
+        case 8: return launch_rkg<9>(visc, g, r, s);
+        default: return -1;
+    }
+}
+
 KernelTimer &residual_timer() {
     static KernelTimer t;
     return t;
-}
-
-int launch_residual(int p, const ResArgs &a, hipStream_t s, bool fixup) {
-    switch (p) {
-        case 1: return launch_res_n<2, 8>(a, s, fixup);
-        case 2: return launch_res_n<3, 2>(a, s, fixup);
-        case 3: return launch_res_n<4, 1>(a, s, fixup);
-        case 4: return launch_res_n<5, 1>(a, s, fixup);
-        case 5: return launch_res_n<6, 1>(a, s, fixup);
-        case 6: return launch_res_n<7, 1>(a, s, fixup);
-        case 7: return launch_res_n<8, 1>(a, s, fixup);
-        case 8: return launch_res_n<9, 1>(a, s, fixup);
-        default: return -1;
-    }
-}
-
-int launch_rk_fixup_stage(int p, const ResArgs &a, const RkArgs &r, hipStream_t s) {
-    switch (p) {
-        case 1: return launch_rkfs_n<2>(a, r, s);
-        case 2: return launch_rkfs_n<3>(a, r, s);
-        case 3: return launch_rkfs_n<4>(a, r, s);
-        case 4: return launch_rkfs_n<5>(a, r, s);
-        case 5: return launch_rkfs_n<6>(a, r, s);
-        case 6: return launch_rkfs_n<7>(a, r, s);
-        case 7: return launch_rkfs_n<8>(a, r, s);
-        case 8: return launch_rkfs_n<9>(a, r, s);
-        default: return -1;
-    }
 }
 
 int launch_rk_stage(const RkArgs &a, hipStream_t s) {

@@ -83,3 +83,29 @@ def test_batched_rk4_matches_oracle_per_problem():
         n = q.size
         assert rel_err(out[off:off + n].reshape(q.shape) - c.q, q - c.q) < TOL
         off += n
+
+
+def test_every_schedule_gives_bitwise_identical_results():
+    """Each schedule (elements per workgroup, persistent grid) computes each element identically."""
+    require_gpu()
+    probs = [W.make_problem(p=p, E=E, L=2.0, A=0.1, mu=mu, seed=120 + p, u_rms=0.3)
+             for p, E, mu in [(1, 3, 0.01), (2, 3, 0.0), (3, 3, 0.01), (4, 2, 0.01), (5, 2, 0.0),
+                              (6, 2, 0.01), (7, 2, 0.01), (8, 2, 0.0)]]
+    cases = [Case(pr) for pr in probs]
+    ps = P.ProblemSet([device_problem(c) for c in cases])
+    qd = torch.cat([to_dev(c.jumpy(0.01, i)) for i, c in enumerate(cases)])
+    ref = ps.residual(qd).clone()
+    dt = torch.tensor([1e-4] * len(probs), dtype=torch.float64, device=DEV)
+    q_rk = qd.clone()
+    ps.rk_step(q_rk, dt, 1)
+    for p in range(1, 9):
+        for v in range(P.schedule_count(p)):
+            ps.set_schedule(p, v)
+            assert torch.equal(ps.residual(qd), ref), (p, v)
+            q2 = qd.clone()
+            ps.rk_step(q2, dt, 1)
+            assert torch.equal(q2, q_rk), (p, v)
+        ps.set_schedule(p, 0)
+    chosen = ps.autotune(qd, reps=1)
+    assert len(chosen) == len(probs)
+    assert torch.equal(ps.residual(qd), ref)
