@@ -65,6 +65,28 @@ def algorithmic_bytes(p, K, viscous):
     return b
 
 
+# HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
+# this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
+# copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
+TRAFFIC = {"sha256": None, "workload": "ns_tgv_p4_e32", "bytes": None}
+KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for_current_kernel(p, K):
+    if TRAFFIC["bytes"] is None or TRAFFIC["sha256"] != kernel_sha():
+        return None
+    return TRAFFIC["bytes"]
+
+
 # ------------------------------------------------------------------------------------------
 def cpu_leg(workload: str, n_sample: int, seed: int = 11):
     """Oracle timing on a bounded element sample (run in a child with one thread)."""
@@ -109,6 +131,106 @@ def run_cpu_baseline(workload: str, n_sample: int):
     return json.loads(res.stdout.strip().splitlines()[-1])
 
 
+
+# ------------------------------------------------------------------------------------------
+# Device setup and the secondary measurements (plain residual per workload, batched RK4, VJP)
+# ------------------------------------------------------------------------------------------
+def device_problem(P, W, prob, dev):
+    import torch
+    x1d, _, _ = P.lgl_operator(prob.p)
+    coords = W.coords(prob, x1d, device=dev)
+    metric, jac = P.metrics(prob.p, coords.reshape(3, -1).contiguous())
+    q = W.state(prob, coords).reshape(-1).contiguous()
+    dt = W.cfl_dt(prob, coords)
+    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(W.neighbours(prob.E), device=dev),
+                   metric=metric, jac=jac, gamma=prob.gamma, R=prob.R, mu=prob.mu, Pr=prob.Pr,
+                   eta=prob.eta, iface_diss=prob.iface_diss, two_point=prob.two_point)
+    return dp, q, dt
+
+
+def timed(fn, reps, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(torch.cuda.current_stream())
+    for _ in range(reps):
+        fn()
+    e1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def plain_rate(P, W, name, dev, reps):
+    import torch
+    prob = W.config(name)
+    dp, q, _ = device_problem(P, W, prob, dev)
+    ps = P.ProblemSet([dp])
+    ps.autotune(q, reps=2)
+    out = torch.empty_like(q)
+    ms = timed(lambda: ps.residual(q, out), reps)
+    ps.status()
+    return {"Mdof_res_per_s": round(prob.n_nodes / (ms * 1e-3) / 1e6, 1), "ms": round(ms, 4),
+            "nodes": prob.n_nodes, "p": prob.p}
+
+
+def vjp_rate(P, W, dev, reps):
+    import torch
+    prob = W.config("vjp_p4_e16")
+    dp, q, _ = device_problem(P, W, prob, dev)
+    ps = P.ProblemSet([dp])
+    ps.autotune(q, reps=2)
+    gb = W.cotangent(prob, 5, device=dev).reshape(-1).contiguous()
+    out = torch.empty_like(q)
+    ms_r = timed(lambda: ps.residual(q, out), reps)
+    ms_v = timed(lambda: ps.residual_vjp(q, gb, out), reps)
+    ps.status()
+    return {"Mdof_vjp_per_s": round(prob.n_nodes / (ms_v * 1e-3) / 1e6, 1), "ms": round(ms_v, 4),
+            "residual_ms": round(ms_r, 4), "vjp_over_residual_cost": round(ms_v / ms_r, 3),
+            "nodes": prob.n_nodes}
+
+
+def batched_rate(P, W, dev, steps, loop_baseline=True):
+    """The heterogeneous batch, `steps` RK4 steps in one graph-replayed call, against advancing
+    the same problems one problem at a time with the plain per-problem path."""
+    import torch
+    probs = W.batch_config()
+    dps, qs, dts = [], [], []
+    for pr in probs:
+        dp, q, dt = device_problem(P, W, pr, dev)
+        dps.append(dp)
+        qs.append(q)
+        dts.append(dt)
+    q = torch.cat(qs)
+    del qs
+    ps = P.ProblemSet(dps)
+    ps.autotune(q, reps=2)
+    dtd = torch.tensor(dts, dtype=torch.float64, device=dev)
+    nodes = ps.total_nodes
+    q_work = q.clone()
+    ms = timed(lambda: ps.rk_step(q_work, dtd, steps), 1, warm=1)
+    ps.status()
+    res = {"problems": len(probs), "nodes": nodes, "rk4_steps": steps, "ms": round(ms, 3),
+           "Mdof_res_per_s": round(4 * steps * nodes / (ms * 1e-3) / 1e6, 1)}
+    if loop_baseline:
+        singles = [P.ProblemSet([d]) for d in dps]
+        offs = [0]
+        for d in dps:
+            offs.append(offs[-1] + 5 * d.nodes)
+        views = [q_work[offs[b]:offs[b + 1]] for b in range(len(dps))]
+        dtv = [dtd[b:b + 1] for b in range(len(dps))]
+
+        def loop():
+            for b, s_ in enumerate(singles):
+                s_.rk_step(views[b], dtv[b], steps)
+
+        ms_loop = timed(loop, 1, warm=1)
+        res["per_problem_loop_ms"] = round(ms_loop, 3)
+        res["batched_speedup_vs_loop"] = round(ms_loop / ms, 2)
+    return res
+
+
 # ------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -120,6 +242,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the plain/batched/VJP secondary measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.cpu_leg:
@@ -139,17 +265,10 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     prob = W.config(args.workload)
-    N = prob.p + 1
-    x1d, _, _ = P.lgl_operator(prob.p)
-    coords = W.coords(prob, x1d, device=dev)
-    metric, jac = P.metrics(prob.p, coords.reshape(3, -1).contiguous())
-    q = W.state(prob, coords).reshape(-1).contiguous()
-    dt = torch.tensor([W.cfl_dt(prob, coords)], dtype=torch.float64, device=dev)
-    del coords
-    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(W.neighbours(prob.E), device=dev),
-                   metric=metric, jac=jac, gamma=prob.gamma, R=prob.R, mu=prob.mu, Pr=prob.Pr,
-                   eta=prob.eta, iface_diss=prob.iface_diss, two_point=prob.two_point)
+    dp, q, dt0 = device_problem(P, W, prob, dev)
+    dt = torch.tensor([dt0], dtype=torch.float64, device=dev)
     ps = P.ProblemSet([dp])
+    schedule = ps.autotune(q, reps=3)[0]
     out = torch.empty_like(q)
 
     def step():
@@ -189,11 +308,30 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = None
+    roof["traffic"] = traffic_for_current_kernel(prob.p, prob.K)
     roof["kernel"] = "k_residual"
     roof["kernel_ms"] = round(kmean, 4)
     roof["hbm_GBps_algorithmic"] = round(hbm, 1)
     roof["fp64_TFLOPs_algorithmic"] = round(alu, 3)
+
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    extra = None
+    if not args.no_extra:
+        extra = {
+            "schedule_variant": schedule,
+            "plain_euler_p3_e4": plain_rate(P, W, "euler_p3_e4", dev, 50),
+            "plain_ns_tgv_p4_e32": plain_rate(P, W, "ns_tgv_p4_e32", dev, 10),
+            "plain_ns_p7_e16": plain_rate(P, W, "ns_p7_e16", dev, 10),
+            "vjp_p4_e16": vjp_rate(P, W, dev, 10),
+            "batched_256_rk4x10": batched_rate(P, W, dev, 10),
+        }
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -213,6 +351,7 @@ def main():
                    "Re": prob.Re, "Ma": prob.Ma, "parallelism": "none (1 GPU)"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "sub": extra,
     }
     print(json.dumps(line), flush=True)
     return 0
