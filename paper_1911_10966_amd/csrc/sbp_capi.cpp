@@ -282,6 +282,8 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
             d.Pr = pr.Pr;
             d.eta = pr.eta;
             d.w_end = host_op(pr.p).w[0];
+            d.isw = 1.0 / d.w_end;
+            d.kap = pr.mu > 0.0 ? pr.mu * pr.gamma * pr.R / ((pr.gamma - 1.0) * pr.Pr) : 0.0;
             d.iface_diss = pr.iface_diss;
             d.two_point = pr.two_point;
             d.dt_index = b;

@@ -63,31 +63,47 @@ __device__ __forceinline__ void primitives(const double q[5], double gm1, Node &
     n.k = n.u1 * n.u1 + n.u2 * n.u2 + n.u3 * n.u3;
     P = gm1 * (q[4] - 0.5 * q[0] * n.k);
     ok = (q[0] > 0.0) && (P > 0.0) && isfinite(q[4]) && isfinite(n.k);
-    n.beta = ok ? 0.5 * q[0] / P : 1.0;
+    n.beta = ok ? 0.5 * q[0] * rcp(P) : 1.0;
     n.lrho = ok ? log(q[0]) : 0.0;
     n.lbeta = ok ? log(n.beta) : 0.0;
 }
 
+// Primitives of a neighbour node without the logarithms (see flux_n<FLUX, true>).
+__device__ __forceinline__ void primitives_nolog(const double q[5], double gm1, Node &n, double &P) {
+    n.rho = q[0];
+    const double ir = rcp(q[0]);
+    n.u1 = q[1] * ir;
+    n.u2 = q[2] * ir;
+    n.u3 = q[3] * ir;
+    n.k = n.u1 * n.u1 + n.u2 * n.u2 + n.u3 * n.u3;
+    P = gm1 * (q[4] - 0.5 * q[0] * n.k);
+    n.beta = 0.5 * q[0] * rcp(P);
+    n.lrho = 0.0;
+    n.lbeta = 0.0;
+}
+
 // Two-point flux F#(a, b) contracted with the vector (n0, n1, n2).
 // FLUX 0: Chandrashekar (entropy conservative), 1: central, 2: Kennedy-Gruber.
-template <int FLUX>
+// LAZY: b.lrho and b.lbeta are not set; they are computed only in the (rare) direct branch.
+template <int FLUX, bool LAZY = false>
 __device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, double n1, double n2,
                                        double gm1, double f[5]) {
     const double ub1 = 0.5 * (a.u1 + b.u1), ub2 = 0.5 * (a.u2 + b.u2), ub3 = 0.5 * (a.u3 + b.u3);
     const double un = ub1 * n0 + ub2 * n1 + ub3 * n2;
     if constexpr (FLUX == 0) {
         const double sr = a.rho + b.rho, dr = a.rho - b.rho;
-        const double isr = rcp(sr);
+        const double sb = a.beta + b.beta, db = a.beta - b.beta;
+        const double irb = rcp(sr * sb);  // one reciprocal for 1/(rho_i + rho_j), 1/(beta_i + beta_j)
+        const double isr = sb * irb;
+        const double isb = sr * irb;
         const double zr = dr * isr, ur = zr * zr;
         double rho_hat;
         if (ur < LOGMEAN_U) rho_hat = 0.5 * sr * series_G(ur);
-        else rho_hat = dr * rcp(a.lrho - b.lrho);
-        const double sb = a.beta + b.beta, db = a.beta - b.beta;
-        const double isb = rcp(sb);
+        else rho_hat = dr * rcp(a.lrho - (LAZY ? log(b.rho) : b.lrho));
         const double zb = db * isb, ub = zb * zb;
         double ibeta_hat;
         if (ub < LOGMEAN_U) ibeta_hat = 2.0 * isb * series_F(ub);
-        else ibeta_hat = (a.lbeta - b.lbeta) * rcp(db);
+        else ibeta_hat = (a.lbeta - (LAZY ? log(b.beta) : b.lbeta)) * rcp(db);
         const double pt = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
         const double fr = rho_hat * un;
         f[0] = fr;
@@ -162,6 +178,45 @@ __device__ __forceinline__ long long xcd_block(long long b, long long B) {
     const long long per = B / X, rem = B % X;
     const long long x = b % X, slot = b / X;
     return x * per + (x < rem ? x : rem) + slot;
+}
+
+// Uncontracted viscous flux F^V_m[c] (m = 0..2; c = 0..2 momentum, 3 energy) from the
+// entropy-variable gradients g[j][c] = dW_{c+1}/dx_j: stresses of eq. tau with
+// dU_k = T (dW_{k+1} + U_k dW_5), heat flux +kappa dT/dx_m with dT = T^2 dW_5.
+__device__ __forceinline__ void visc_flux_full(const double g[3][4], double u1, double u2, double u3,
+                                               double T, double mu, double kap, double F[3][4]) {
+    const double u[3] = {u1, u2, u3};
+    double du[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) du[k][j] = T * fma(u[k], g[j][3], g[j][k]);
+    const double div23 = (2.0 / 3.0) * (du[0][0] + du[1][1] + du[2][2]);
+    const double T2k = kap * T * T;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) F[m][i] = mu * (du[i][m] + du[m][i] - (i == m ? div23 : 0.0));
+        F[m][3] = fma(F[m][0], u[0], fma(F[m][1], u[1], fma(F[m][2], u[2], T2k * g[m][3])));
+    }
+}
+
+// sum_m n_m F^V_m for the rank-one gradient g_j = n_j dw / J (the interior-penalty term):
+// dU = v n^T / J with v_k = T (dw_k + U_k dw_5), which gives momentum (mu/J)(|n|^2 v + (v.n) n / 3)
+// and energy U . momentum + kappa T^2 |n|^2 dw_5 / J.
+__device__ __forceinline__ void visc_flux_rank1(double n0, double n1, double n2, double iJ,
+                                                const double dw[4], double u1, double u2, double u3,
+                                                double T, double mu, double kap, double out[4]) {
+    const double v0 = T * fma(u1, dw[3], dw[0]);
+    const double v1 = T * fma(u2, dw[3], dw[1]);
+    const double v2 = T * fma(u3, dw[3], dw[2]);
+    const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+    const double vn = v0 * n0 + v1 * n1 + v2 * n2;
+    const double c1 = mu * iJ * nn, c2 = mu * iJ * vn * (1.0 / 3.0);
+    out[0] = fma(c1, v0, c2 * n0);
+    out[1] = fma(c1, v1, c2 * n1);
+    out[2] = fma(c1, v2, c2 * n2);
+    out[3] = fma(u1, out[0], fma(u2, out[1], fma(u3, out[2], kap * T * T * nn * iJ * dw[3])));
 }
 
 template <int N>

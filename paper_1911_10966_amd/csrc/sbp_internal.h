@@ -23,6 +23,8 @@ struct ResArgs {
     long long nodes;
     double gamma, R, mu, Pr, eta;
     double w_end;          // end weight of the 1-D norm
+    double isw;            // 1 / w_end
+    double kap;            // thermal conductivity mu c_p / Pr
     int iface_diss;
     int two_point;
 };
@@ -40,6 +42,8 @@ struct ProbDev {
     long long off;
     double gamma, R, mu, Pr, eta;
     double w_end;
+    double isw;
+    double kap;
     int iface_diss;
     int two_point;
     int dt_index;
@@ -74,6 +78,7 @@ struct RkGroupArgs {
 struct Schedule {
     int epw;
     int persistent;
+    int wpe;        // minimum waves per SIMD requested from the register allocator (0: none)
 };
 int schedule_count(int p);
 Schedule schedule_of(int p, int variant);

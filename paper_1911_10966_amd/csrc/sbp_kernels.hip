@@ -12,13 +12,15 @@
 namespace sbp {
 namespace {
 
+constexpr int LDS_FIELDS = 24;  // doubles of LDS per node in the residual kernel
+
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
 template <int N, int EPW, bool VISC, int FLUX>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
                                               const double *s_D) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
     constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6, F_K = 7;
-    constexpr int F_A = 8, F_MSG = 11;
+    constexpr int F_A0 = 8, F_A1 = 11, F_MSG0 = 14, F_MSG1 = 19;
 
     const int tid = threadIdx.x;
     const int slot = tid / N3;
@@ -31,7 +33,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     const long long nodes = a.nodes;
     const long long g = e * N3 + ln;
     const double gm1 = a.gamma - 1.0;
-    const double w_end = a.w_end;
+    const double isw = a.isw;
 
     // ---- node-local primitives --------------------------------------------------------------
     double q[5];
@@ -71,13 +73,17 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     // ---- inviscid volume term: -sum_l sum_j D(i_l, j_l) (A_l,i + A_l,j) . F#(q_i, q_j) ----------
-    // (the j = i terms cancel exactly against the own-flux part of the interface SAT)
+    // (the j = i terms cancel exactly against the own-flux part of the interface SAT).  The metric
+    // rows of consecutive directions and the mailboxes of consecutive rounds alternate between two
+    // LDS areas, so one barrier per round suffices.
+    int round = 0;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
+        const int fa = (l & 1) ? F_A1 : F_A0;
         if (tid < NODES) {
-            s_buf[(F_A + 0) * NODES + tid] = A[l][0];
-            s_buf[(F_A + 1) * NODES + tid] = A[l][1];
-            s_buf[(F_A + 2) * NODES + tid] = A[l][2];
+            s_buf[(fa + 0) * NODES + tid] = A[l][0];
+            s_buf[(fa + 1) * NODES + tid] = A[l][1];
+            s_buf[(fa + 2) * NODES + tid] = A[l][2];
         }
         __syncthreads();
         const int il = idx[l];
@@ -93,33 +99,33 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             o.lrho = s_buf[F_LR * NODES + pn];
             o.lbeta = s_buf[F_LB * NODES + pn];
             o.k = s_buf[F_K * NODES + pn];
-            const double n0 = A[l][0] + s_buf[(F_A + 0) * NODES + pn];
-            const double n1 = A[l][1] + s_buf[(F_A + 1) * NODES + pn];
-            const double n2 = A[l][2] + s_buf[(F_A + 2) * NODES + pn];
+            const double n0 = A[l][0] + s_buf[(fa + 0) * NODES + pn];
+            const double n1 = A[l][1] + s_buf[(fa + 1) * NODES + pn];
+            const double n2 = A[l][2] + s_buf[(fa + 2) * NODES + pn];
             flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
             return pn;
         };
 #pragma unroll
         for (int r = 1; 2 * r < N; ++r) {
+            const int fm = (round & 1) ? F_MSG1 : F_MSG0;
+            ++round;
             int b = il + r;
             if (b >= N) b -= N;
-            double f[5];
-            int pn = 0;
             if (tid < NODES) {
-                pn = pair(b, f);
+                double f[5];
+                const int pn = pair(b, f);
                 const double dab = s_D[il * N + b], dba = s_D[b * N + il];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     acc[c] = fma(-dab, f[c], acc[c]);
-                    s_buf[(F_MSG + c) * NODES + pn] = dba * f[c];
+                    s_buf[(fm + c) * NODES + pn] = dba * f[c];
                 }
             }
             __syncthreads();
             if (tid < NODES) {
 #pragma unroll
-                for (int c = 0; c < 5; ++c) acc[c] -= s_buf[(F_MSG + c) * NODES + tid];
+                for (int c = 0; c < 5; ++c) acc[c] -= s_buf[(fm + c) * NODES + tid];
             }
-            __syncthreads();
         }
         if constexpr (N % 2 == 0) {
             if (tid < NODES) {
@@ -132,71 +138,22 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 for (int c = 0; c < 5; ++c) acc[c] = fma(-dab, f[c], acc[c]);
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
 
-    // ---- inviscid interface SAT: -(s/w_end) F#(q_i, q_nu) . nbar, Lax-Friedrichs dissipation ----
-    const double isw = 1.0 / w_end;
-    if (active) {
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int il = idx[l];
-            if (il != 0 && il != N - 1) continue;
-            const int side = (il == N - 1) ? 1 : 0;
-            const double s = side ? 1.0 : -1.0;
-            const long long nb = a.nbr[e * 6 + 2 * l + side];
-            if (nb < 0 || nb >= a.K) {
-                atomicOr(a.status, FLAG_MESH);
-                continue;
-            }
-            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
-            double qn[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
-            const double An0 = a.metric[(3 * l + 0) * nodes + pg];
-            const double An1 = a.metric[(3 * l + 1) * nodes + pg];
-            const double An2 = a.metric[(3 * l + 2) * nodes + pg];
-            Node o;
-            double Pn;
-            bool okn;
-            primitives(qn, gm1, o, Pn, okn);
-            const double n0 = 0.5 * (A[l][0] + An0), n1 = 0.5 * (A[l][1] + An1),
-                         n2 = 0.5 * (A[l][2] + An2);
-            double f[5];
-            flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
-#pragma unroll
-            for (int c = 0; c < 5; ++c) acc[c] = fma(-s * isw, f[c], acc[c]);
-            if (a.iface_diss) {
-                const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-                const double li = fabs(me.u1 * n0 + me.u2 * n1 + me.u3 * n2) +
-                                  sqrt(a.gamma * Pme / me.rho) * nn;
-                const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) +
-                                  sqrt(a.gamma * Pn / o.rho) * nn;
-                const double lam = fmax(li, lo);
-                const double cf = -0.5 * lam * isw;
-#pragma unroll
-                for (int c = 0; c < 5; ++c) acc[c] = fma(cf, q[c] - qn[c], acc[c]);
-            }
-        }
-    }
-
-    const double iJ = 1.0 / J;
-
+    const double iJ = rcp(J);
+    const double mu = a.mu, kap = a.kap;
+    double T = 1.0, w[4] = {0.0, 0.0, 0.0, 0.0}, th[3][4];
     if constexpr (VISC) {
-        // ---- viscous operator in entropy variables (BR1 gradient, divergence, SAT^V, IP) --------
-        const double mu = a.mu;
-        const double kap = a.mu * a.gamma * a.R / ((a.gamma - 1.0) * a.Pr);
-        const double iT = 2.0 * a.R * me.beta;  // 1/T
-        const double T = 1.0 / iT;
-        const double w[4] = {me.u1 * iT, me.u2 * iT, me.u3 * iT, -iT};
-        __syncthreads();
+        // ---- BR1 gradient theta_a = D_a w from the lines (w = (U/T, -1/T); W_1 is not needed) --
+        const double iT = 2.0 * a.R * me.beta;
+        T = rcp(iT);
+        w[0] = me.u1 * iT; w[1] = me.u2 * iT; w[2] = me.u3 * iT; w[3] = -iT;
         if (tid < NODES) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) s_buf[c * NODES + tid] = w[c];
         }
         __syncthreads();
-        double th[3][4];
-        double wn_face[3][4];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -212,56 +169,87 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 }
             }
         }
-        // SAT^theta = (s/(2 w_end)) (w_nu - w_i) on faces of direction d
-        double Jn_face[3], An_face[3][3], un_face[3][3], Tn_face[3];
-        bool face[3] = {false, false, false};
-        long long nbf[3] = {0, 0, 0};
-        if (active) {
+    }
+
+    // ---- faces: EC interface flux, Lax-Friedrichs dissipation, SAT^theta, interior penalty ----
+    int faces = 0;
+    if (active) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int il = idx[d];
-                if (il != 0 && il != N - 1) continue;
-                const int side = (il == N - 1) ? 1 : 0;
-                const double s = side ? 1.0 : -1.0;
-                const long long nb = a.nbr[e * 6 + 2 * d + side];
-                if (nb < 0 || nb >= a.K) continue;
-                face[d] = true;
-                nbf[d] = nb;
-                const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
-                double qn[5];
+        for (int l = 0; l < 3; ++l) {
+            const int il = idx[l];
+            if (il != 0 && il != N - 1) continue;
+            const int side = (il == N - 1) ? 1 : 0;
+            const double s = side ? 1.0 : -1.0;
+            const long long nb = a.nbr[e * 6 + 2 * l + side];
+            if (nb < 0 || nb >= a.K) {
+                atomicOr(a.status, FLAG_MESH);
+                continue;
+            }
+            faces |= 1 << l;
+            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
+            double qn[5];
 #pragma unroll
-                for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
-                const double irn = 1.0 / qn[0];
-                const double v1 = qn[1] * irn, v2 = qn[2] * irn, v3 = qn[3] * irn;
-                const double Pn = gm1 * (qn[4] - 0.5 * qn[0] * (v1 * v1 + v2 * v2 + v3 * v3));
-                const double iTn = qn[0] * a.R / Pn;
-                wn_face[d][0] = v1 * iTn;
-                wn_face[d][1] = v2 * iTn;
-                wn_face[d][2] = v3 * iTn;
-                wn_face[d][3] = -iTn;
-                un_face[d][0] = v1;
-                un_face[d][1] = v2;
-                un_face[d][2] = v3;
-                Tn_face[d] = 1.0 / iTn;
-                Jn_face[d] = a.jac[pg];
+            for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
+            const double An0 = a.metric[(3 * l + 0) * nodes + pg];
+            const double An1 = a.metric[(3 * l + 1) * nodes + pg];
+            const double An2 = a.metric[(3 * l + 2) * nodes + pg];
+            Node o;
+            double Pn;
+            primitives_nolog(qn, gm1, o, Pn);
+            const double n0 = 0.5 * (A[l][0] + An0), n1 = 0.5 * (A[l][1] + An1),
+                         n2 = 0.5 * (A[l][2] + An2);
+            double f[5];
+            flux_n<FLUX, true>(me, o, n0, n1, n2, gm1, f);
 #pragma unroll
-                for (int m = 0; m < 3; ++m) An_face[d][m] = a.metric[(3 * d + m) * nodes + pg];
-                const double cf = 0.5 * s * isw;
+            for (int c = 0; c < 5; ++c) acc[c] = fma(-s * isw, f[c], acc[c]);
+            if (a.iface_diss) {
+                const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+                const double li = fabs(me.u1 * n0 + me.u2 * n1 + me.u3 * n2) +
+                                  sqrt(a.gamma * Pme / me.rho) * nn;
+                const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) +
+                                  sqrt(a.gamma * Pn / o.rho) * nn;
+                const double cf = -0.5 * fmax(li, lo) * isw;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) th[d][c] = fma(cf, wn_face[d][c] - w[c], th[d][c]);
+                for (int c = 0; c < 5; ++c) acc[c] = fma(cf, q[c] - qn[c], acc[c]);
+            }
+            if constexpr (VISC) {
+                const double iTn = 2.0 * a.R * o.beta;
+                const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
+                const double ct = 0.5 * s * isw;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) th[l][c] = fma(ct, wn[c] - w[c], th[l][c]);
+                if (a.eta != 0.0) {
+                    const double iJn = rcp(a.jac[pg]);
+                    double dw[4], pi_[4], pn_[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dw[c] = w[c] - wn[c];
+                    visc_flux_rank1(A[l][0], A[l][1], A[l][2], iJ, dw, me.u1, me.u2, me.u3, T, mu,
+                                    kap, pi_);
+                    visc_flux_rank1(An0, An1, An2, iJn, dw, o.u1, o.u2, o.u3, rcp(iTn), mu, kap, pn_);
+                    const double cf = -0.5 * a.eta * isw;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cf, pi_[c] + pn_[c], acc[c + 1]);
+                }
             }
         }
-        // physical gradient g_j = sum_d A_dj theta_d / J, viscous flux, contravariant fluxes fhat_l
+    }
+
+    if constexpr (VISC) {
+        // ---- viscous flux, contravariant fluxes fhat_l, traces, divergence, own SAT^V ----------
         double gr[3][4];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 gr[j][c] = (A[0][j] * th[0][c] + A[1][j] * th[1][c] + A[2][j] * th[2][c]) * iJ;
+        double FV[3][4];
+        visc_flux_full(gr, me.u1, me.u2, me.u3, T, mu, kap, FV);
         double fh[3][4];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) visc_flux_contract(gr, me.u1, me.u2, me.u3, T, mu, kap, A[l], fh[l]);
-        // face traces of fhat_l for the neighbours' SAT^V
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                fh[l][c] = fma(A[l][0], FV[0][c], fma(A[l][1], FV[1][c], A[l][2] * FV[2][c]));
         if (active) {
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
@@ -272,9 +260,13 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 double *tr = a.trace + ((e * 6 + 2 * l + side) * 4) * N2 + t;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) tr[c * N2] = fh[l][c];
+                if (faces & (1 << l)) {
+                    const double cs = -0.5 * (side ? 1.0 : -1.0) * isw;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cs, fh[l][c], acc[c + 1]);
+                }
             }
         }
-        // divergence sum_l D_l fhat_l
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             __syncthreads();
@@ -294,38 +286,6 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 }
             }
         }
-        // own part of SAT^V and interior penalty
-        if (active) {
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                if (!face[l]) continue;
-                const double s = (idx[l] == N - 1) ? 1.0 : -1.0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c + 1] = fma(-0.5 * s * isw, fh[l][c], acc[c + 1]);
-                if (a.eta != 0.0) {
-                    double dw[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) dw[c] = w[c] - wn_face[l][c];
-                    double gi[3][4], gn[3][4];
-                    const double iJn = 1.0 / Jn_face[l];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            gi[j][c] = A[l][j] * dw[c] * iJ;
-                            gn[j][c] = An_face[l][j] * dw[c] * iJn;
-                        }
-                    double pi_[4], pn_[4];
-                    visc_flux_contract(gi, me.u1, me.u2, me.u3, T, mu, kap, A[l], pi_);
-                    visc_flux_contract(gn, un_face[l][0], un_face[l][1], un_face[l][2], Tn_face[l], mu,
-                                       kap, An_face[l], pn_);
-                    const double cf = -0.5 * a.eta * isw;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cf, pi_[c] + pn_[c], acc[c + 1]);
-                }
-            }
-        }
-        (void)nbf;
     }
 
     if (active) {
@@ -362,6 +322,8 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
     a.Pr = P.Pr;
     a.eta = P.eta;
     a.w_end = P.w_end;
+    a.isw = P.isw;
+    a.kap = P.kap;
     a.iface_diss = P.iface_diss;
     a.two_point = P.two_point;
     return a;
@@ -370,11 +332,12 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
 // Residual over a group of problems.  Non-persistent: one block per element tile.  Persistent:
 // a grid sized to the resident capacity walks the tiles (the grid is a multiple of the XCD count,
 // so the XCD-contiguous remap of tile indices still holds).
-template <int N, int EPW, bool VISC, int FLUX, bool PERSIST>
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE>
 __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
+__attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
 k_residual(const GroupArgs g) {
     constexpr int N2 = N * N, NODES = EPW * N * N * N;
-    __shared__ double s_buf[16 * NODES];
+    __shared__ double s_buf[LDS_FIELDS * NODES];
     __shared__ double s_D[N2];
     if (threadIdx.x < N2) s_D[threadIdx.x] = g.D[threadIdx.x];
     if constexpr (!PERSIST) {
@@ -571,11 +534,11 @@ k_metrics(const double *x, double *metric, double *jac, const double *D, long lo
 
 // ---- launchers ---------------------------------------------------------------------------
 // Schedules per degree: {elements per workgroup, persistent grid}.  Entry 0 is the default.
-constexpr Schedule kSched2[] = {{8, 0}, {16, 0}, {8, 1}, {16, 1}};
-constexpr Schedule kSched3[] = {{2, 0}, {7, 0}, {2, 1}, {7, 1}};
-constexpr Schedule kSched4[] = {{1, 0}, {2, 0}, {4, 0}, {1, 1}, {2, 1}};
-constexpr Schedule kSched5[] = {{1, 0}, {2, 0}, {1, 1}, {2, 1}};
-constexpr Schedule kSchedBig[] = {{1, 0}, {1, 1}};
+constexpr Schedule kSched2[] = {{8, 0, 0}, {16, 0, 0}, {8, 1, 0}, {16, 1, 0}, {8, 0, 4}};
+constexpr Schedule kSched3[] = {{2, 0, 0}, {7, 0, 0}, {2, 1, 0}, {7, 1, 0}, {7, 0, 4}};
+constexpr Schedule kSched4[] = {{1, 0, 0}, {2, 0, 0}, {4, 0, 0}, {1, 1, 0}, {2, 1, 0}, {1, 0, 4}, {2, 0, 4}};
+constexpr Schedule kSched5[] = {{1, 0, 0}, {2, 0, 0}, {1, 1, 0}, {2, 1, 0}, {1, 0, 4}, {2, 0, 4}, {1, 0, 3}};
+constexpr Schedule kSchedBig[] = {{1, 0, 0}, {1, 1, 0}, {1, 0, 4}, {1, 0, 3}};
 
 int device_cus() {
     static int cus = 0;
@@ -588,10 +551,10 @@ int device_cus() {
     return cus;
 }
 
-template <int N, int EPW, bool VISC, int FLUX, bool PERSIST>
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE = 0>
 int launch_res_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
-    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST>;
+    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST, WPE>;
     long long grid = g.total_blocks;
     if (PERSIST) {
         static int per_cu = 0;
@@ -627,9 +590,10 @@ int launch_res_e(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
     }
 }
 
-template <int N, int EPW, bool PERSIST>
+template <int N, int EPW, bool PERSIST, int WPE = 0>
 int launch_res_e0(bool visc, const GroupArgs &g, hipStream_t s) {
-    return visc ? launch_res_k<N, EPW, true, 0, PERSIST>(g, s) : launch_res_k<N, EPW, false, 0, PERSIST>(g, s);
+    return visc ? launch_res_k<N, EPW, true, 0, PERSIST, WPE>(g, s)
+                : launch_res_k<N, EPW, false, 0, PERSIST, WPE>(g, s);
 }
 
 template <int N>
@@ -679,20 +643,23 @@ int launch_group_residual(int p, bool visc, int flux, int variant, const GroupAr
     const bool P1 = sc.persistent != 0;
     if (flux == 0) {
 #define SBP_CASE(NN, EE)                                                                \
-    if (sc.epw == EE) rc = P1 ? launch_res_e0<NN, EE, true>(visc, g, s)                 \
-                              : launch_res_e0<NN, EE, false>(visc, g, s);
+    if (sc.epw == EE && sc.wpe == 0) rc = P1 ? launch_res_e0<NN, EE, true>(visc, g, s)  \
+                                             : launch_res_e0<NN, EE, false>(visc, g, s);
+#define SBP_CASEW(NN, EE, WW)                                                           \
+    if (sc.epw == EE && sc.wpe == WW && !P1) rc = launch_res_e0<NN, EE, false, WW>(visc, g, s);
         switch (p) {
-            case 1: SBP_CASE(2, 8) SBP_CASE(2, 16) break;
-            case 2: SBP_CASE(3, 2) SBP_CASE(3, 7) break;
-            case 3: SBP_CASE(4, 1) SBP_CASE(4, 2) SBP_CASE(4, 4) break;
-            case 4: SBP_CASE(5, 1) SBP_CASE(5, 2) break;
-            case 5: SBP_CASE(6, 1) break;
-            case 6: SBP_CASE(7, 1) break;
-            case 7: SBP_CASE(8, 1) break;
-            case 8: SBP_CASE(9, 1) break;
+            case 1: SBP_CASE(2, 8) SBP_CASE(2, 16) SBP_CASEW(2, 8, 4) break;
+            case 2: SBP_CASE(3, 2) SBP_CASE(3, 7) SBP_CASEW(3, 7, 4) break;
+            case 3: SBP_CASE(4, 1) SBP_CASE(4, 2) SBP_CASE(4, 4) SBP_CASEW(4, 1, 4) SBP_CASEW(4, 2, 4) break;
+            case 4: SBP_CASE(5, 1) SBP_CASE(5, 2) SBP_CASEW(5, 1, 4) SBP_CASEW(5, 2, 4) SBP_CASEW(5, 1, 3) break;
+            case 5: SBP_CASE(6, 1) SBP_CASEW(6, 1, 4) SBP_CASEW(6, 1, 3) break;
+            case 6: SBP_CASE(7, 1) SBP_CASEW(7, 1, 4) SBP_CASEW(7, 1, 3) break;
+            case 7: SBP_CASE(8, 1) SBP_CASEW(8, 1, 4) SBP_CASEW(8, 1, 3) break;
+            case 8: SBP_CASE(9, 1) SBP_CASEW(9, 1, 4) SBP_CASEW(9, 1, 3) break;
             default: return -1;
         }
 #undef SBP_CASE
+#undef SBP_CASEW
     } else {
         switch (p) {
             case 1: rc = launch_res_e<2, 8, false>(visc, flux, g, s); break;
