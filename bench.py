@@ -68,7 +68,11 @@ def algorithmic_bytes(p, K, viscous):
 # HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
 # this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
 # copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
-TRAFFIC = {"sha256": None, "workload": "ns_tgv_p4_e32", "bytes": None}
+TRAFFIC = {"sha256": "ef28b44f0de467253ee8f39dd8c4abd5cbb51009e86332e867f9631a068aed5f",
+           "workload": "ns_tgv_p4_e32",
+           # bytes per launch by residual schedule index (degree 4)
+           "bytes": {0: 1142004872, 1: 1180406190, 2: 1043473975, 3: 1031049168, 4: 1141587051,
+                     5: 1170930312, 6: 1816568060}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 
@@ -81,10 +85,10 @@ def kernel_sha():
     return h.hexdigest()
 
 
-def traffic_for_current_kernel(p, K):
-    if TRAFFIC["bytes"] is None or TRAFFIC["sha256"] != kernel_sha():
+def traffic_for_current_kernel(workload, schedule):
+    if TRAFFIC["sha256"] != kernel_sha() or workload != TRAFFIC["workload"]:
         return None
-    return TRAFFIC["bytes"]
+    return TRAFFIC["bytes"].get(schedule)
 
 
 # ------------------------------------------------------------------------------------------
@@ -308,7 +312,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = traffic_for_current_kernel(prob.p, prob.K)
+    roof["traffic"] = traffic_for_current_kernel(args.workload, schedule)
+    roof["schedule"] = schedule
     roof["kernel"] = "k_residual"
     roof["kernel_ms"] = round(kmean, 4)
     roof["hbm_GBps_algorithmic"] = round(hbm, 1)
