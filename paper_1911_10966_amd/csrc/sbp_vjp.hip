@@ -43,6 +43,7 @@ struct NodeBar {
 };
 
 // Reverse of flux_n<0> (Chandrashekar flux contracted with a constant vector n).
+template <bool LAZY = false>
 __device__ __forceinline__ void flux_n_vjp(const Node &a, const Node &b, double n0, double n1,
                                            double n2, double gm1, const double fb[5], NodeBar &ab,
                                            NodeBar &bb) {
@@ -57,7 +58,7 @@ __device__ __forceinline__ void flux_n_vjp(const Node &a, const Node &b, double 
         Gr = series_G(ur);
         rho_hat = 0.5 * sr * Gr;
     } else {
-        iLr = rcp(a.lrho - b.lrho);
+        iLr = rcp(a.lrho - (LAZY ? log(b.rho) : b.lrho));
         rho_hat = dr * iLr;
     }
     const double sb = a.beta + b.beta, db = a.beta - b.beta;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void flux_n_vjp(const Node &a, const Node &b, double 
         ibh = 2.0 * isb * Fb;
     } else {
         idb = rcp(db);
-        ibh = (a.lbeta - b.lbeta) * idb;
+        ibh = (a.lbeta - (LAZY ? log(b.beta) : b.lbeta)) * idb;
     }
     const double pt = 0.5 * sr * isb;
     const double fr = rho_hat * un;
@@ -114,7 +115,7 @@ __device__ __forceinline__ void flux_n_vjp(const Node &a, const Node &b, double 
         dbb += zbb * isb;
         isbb += zbb * db;
     } else {
-        const double Lb = a.lbeta - b.lbeta;
+        const double Lb = a.lbeta - (LAZY ? log(b.beta) : b.lbeta);
         lbb = ibhb * idb;
         dbb -= ibhb * Lb * idb * idb;
     }
@@ -188,6 +189,41 @@ __device__ __forceinline__ void visc_flux_vjp(const double g[3][4], const double
             ub[k] += T * g[j][3] * dub[k][j];
             Tb += fma(u[k], g[j][3], g[j][k]) * dub[k][j];
         }
+}
+
+// Reverse of visc_flux_rank1 (the interior-penalty flux): accumulates the cotangents of dw, U, T
+// for the output cotangent ob.
+__device__ __forceinline__ void visc_flux_rank1_vjp(double n0, double n1, double n2, double iJ,
+                                                    const double dw[4], const double u[3], double T,
+                                                    double mu, double kap, const double ob[4],
+                                                    double dwb[4], double ub[3], double &Tb) {
+    const double n[3] = {n0, n1, n2};
+    double v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = T * fma(u[k], dw[3], dw[k]);
+    const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+    const double vn = v[0] * n0 + v[1] * n1 + v[2] * n2;
+    const double c1 = mu * iJ * nn, c2 = mu * iJ * vn * (1.0 / 3.0);
+    double oe[3], c2b = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double out = fma(c1, v[k], c2 * n[k]);
+        ub[k] = fma(ob[3], out, ub[k]);
+        oe[k] = fma(ob[3], u[k], ob[k]);
+        c2b = fma(oe[k], n[k], c2b);
+    }
+    const double vnb = c2b * mu * iJ * (1.0 / 3.0);
+    const double t3 = kap * T * T * nn * iJ;
+    dwb[3] = fma(ob[3], t3, dwb[3]);
+    Tb += ob[3] * 2.0 * kap * T * nn * iJ * dw[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double vb = fma(c1, oe[k], vnb * n[k]);
+        dwb[k] = fma(T, vb, dwb[k]);
+        dwb[3] = fma(T * u[k], vb, dwb[3]);
+        ub[k] = fma(T * dw[3], vb, ub[k]);
+        Tb += fma(u[k], dw[3], dw[k]) * vb;
+    }
 }
 
 // Cotangents of (rho, U, beta, P, T) of a node mapped to its conservative variables, with
@@ -508,7 +544,7 @@ k_vjp_main(const VjpArgs a) {
     }
     const double mu = a.mu;
     const double kap = a.mu * a.gamma * a.R / ((a.gamma - 1.0) * a.Pr);
-    const double iJ = 1.0 / J;
+    const double iJ = rcp(J);
     if (active) {
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -520,7 +556,7 @@ k_vjp_main(const VjpArgs a) {
             if (nb < 0 || nb >= a.K) continue;
             const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
             double qn[5], rbn[5];
-            const double iJn = 1.0 / a.jac[pg];
+            const double iJn = rcp(a.jac[pg]);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 qn[c] = a.q[c * nodes + pg];
@@ -531,15 +567,14 @@ k_vjp_main(const VjpArgs a) {
             for (int m = 0; m < 3; ++m) An[m] = a.metric[(3 * l + m) * nodes + pg];
             Node o;
             double Pn;
-            bool okn;
-            primitives(qn, gm1, o, Pn, okn);
+            primitives_nolog(qn, gm1, o, Pn);
             const double n0 = 0.5 * (A[l][0] + An[0]), n1 = 0.5 * (A[l][1] + An[1]),
                          n2 = 0.5 * (A[l][2] + An[2]);
             double fb[5];
 #pragma unroll
             for (int c = 0; c < 5; ++c) fb[c] = -s * isw * (rb[c] - rbn[c]);
             NodeBar ab, bb;
-            flux_n_vjp(me, o, n0, n1, n2, gm1, fb, ab, bb);
+            flux_n_vjp<true>(me, o, n0, n1, n2, gm1, fb, ab, bb);
             double ra[5];
             reduce_bar(me, ab, ra);
 #pragma unroll
@@ -579,39 +614,25 @@ k_vjp_main(const VjpArgs a) {
                     // with cotangent rbar_i - rbar_nu (the neighbour's term is -X)
                     const double iTn = 2.0 * a.R * o.beta;
                     const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
-                    double dw[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) dw[c] = wme[c] - wn[c];
+                    double dw[4], ob[4], dwb[4] = {0.0, 0.0, 0.0, 0.0};
                     const double cf = -0.5 * a.eta * isw;
-                    double Fb_i[3][4], Fb_n[3][4], gi[3][4], gn[3][4];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            const double xb = cf * (rb[c + 1] - rbn[c + 1]);
-                            Fb_i[m][c] = A[l][m] * xb;
-                            Fb_n[m][c] = An[m] * xb;
-                            gi[m][c] = A[l][m] * dw[c] * iJ;
-                            gn[m][c] = An[m] * dw[c] * iJn;
-                        }
-                    double gbi[3][4], gbn[3][4];
-                    double umv[3] = {me.u1, me.u2, me.u3};
-                    double unv[3] = {o.u1, o.u2, o.u3};
-                    double ubi[3] = {0.0, 0.0, 0.0}, ubn[3] = {0.0, 0.0, 0.0};
-                    double Tbn = 0.0;
-                    visc_flux_vjp(gi, umv, Tme, mu, kap, Fb_i, gbi, ubi, Tb);
-                    visc_flux_vjp(gn, unv, 1.0 / iTn, mu, kap, Fb_n, gbn, ubn, Tbn);
+                    for (int c = 0; c < 4; ++c) {
+                        dw[c] = wme[c] - wn[c];
+                        ob[c] = cf * (rb[c + 1] - rbn[c + 1]);
+                    }
+                    const double umv[3] = {me.u1, me.u2, me.u3};
+                    const double unv[3] = {o.u1, o.u2, o.u3};
+                    double ubi[3] = {0.0, 0.0, 0.0}, ubn[3] = {0.0, 0.0, 0.0}, Tbn = 0.0;
+                    visc_flux_rank1_vjp(A[l][0], A[l][1], A[l][2], iJ, dw, umv, Tme, mu, kap, ob, dwb,
+                                        ubi, Tb);
+                    visc_flux_rank1_vjp(An[0], An[1], An[2], iJn, dw, unv, rcp(iTn), mu, kap, ob, dwb,
+                                        ubn, Tbn);
                     acc[1] += ubi[0];
                     acc[2] += ubi[1];
                     acc[3] += ubi[2];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        double dwb = 0.0;
-#pragma unroll
-                        for (int j = 0; j < 3; ++j)
-                            dwb += A[l][j] * gbi[j][c] * iJ + An[j] * gbn[j][c] * iJn;
-                        wb[c] += dwb;
-                    }
+                    for (int c = 0; c < 4; ++c) wb[c] += dwb[c];
                 }
             }
         }
