@@ -235,6 +235,43 @@ def batched_rate(P, W, dev, steps, loop_baseline=True):
     return res
 
 
+def cost_experiment(P, W, dev, steps):
+    """The paper's cost-of-entropy-stability test on one MI355X: Taylor-Green vortex (Re = 1600,
+    Ma = 0.05, periodic box of side 2 pi, Cartesian elements) at 256^3 DOFs for p = 1, 3, 7 with the
+    ES-C (Chandrashekar), SF-KG (Kennedy-Gruber) and DC volume terms; time per residual and per
+    classical RK4 step.  The paper's figures (64 Haswell cores, DOPRI5 steps) are quoted as
+    context."""
+    import math
+    import torch
+    paper = {1: {"ES-C": 3.1798, "SF-KG": 2.8634, "DC": 2.7771},
+             3: {"ES-C": 2.5059, "SF-KG": 2.01675, "DC": 1.9593},
+             7: {"ES-C": 2.6099, "SF-KG": 1.73415, "DC": 1.5335}}
+    out = {"dofs": 256 ** 3, "box": "2pi periodic, Cartesian", "Ma": 0.05, "Re": 1600, "results": []}
+    for p in (1, 3, 7):
+        E = 256 // (p + 1)
+        for name, tp in (("ES-C", 0), ("SF-KG", 2), ("DC", 3)):
+            Ma = 0.05
+            prob = W.make_problem(name=f"tgv_p{p}", p=p, E=E, L=2.0 * math.pi, A=0.0, gamma=1.4,
+                                  R=1.0 / (1.4 * Ma * Ma), mu=1.0 / 1600.0, Pr=0.72, init="tgv",
+                                  Ma=Ma, two_point=tp)
+            dp, q, dt0 = device_problem(P, W, prob, dev)
+            ps = P.ProblemSet([dp])
+            sched = ps.autotune(q, reps=2)[0] if tp == 0 else 0
+            out_t = torch.empty_like(q)
+            ms_res = timed(lambda: ps.residual(q, out_t), 5)
+            dt = torch.tensor([dt0], dtype=torch.float64, device=dev)
+            ms_rk = timed(lambda: ps.rk_step(q, dt, steps), 1, warm=1) / steps
+            ps.status()
+            out["results"].append({"p": p, "elements": prob.K, "scheme": name, "schedule": sched,
+                                   "ms_per_residual": round(ms_res, 3),
+                                   "ms_per_rk4_step": round(ms_rk, 3),
+                                   "Mdof_res_per_s": round(prob.n_nodes / (ms_res * 1e-3) / 1e6, 1),
+                                   "paper_s_per_dopri5_step_64_haswell_cores": paper[p][name]})
+            del ps, dp, q, out_t
+            torch.cuda.empty_cache()
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -246,6 +283,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--cost-experiment", action="store_true",
+                    help="run only the ES-C / SF-KG / DC cost comparison at 256^3 DOFs and print it")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the plain/batched/VJP secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -268,6 +307,9 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.cost_experiment:
+        print(json.dumps({"cost_of_entropy_stability": cost_experiment(P, W, dev, 5)}), flush=True)
+        return 0
     prob = W.config(args.workload)
     dp, q, dt0 = device_problem(P, W, prob, dev)
     dt = torch.tensor([dt0], dtype=torch.float64, device=dev)

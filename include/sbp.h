@@ -50,6 +50,8 @@ extern "C" {
 #define SBP_FLUX_CHANDRASHEKAR 0 /* entropy-conservative two-point flux (ES-C)                 */
 #define SBP_FLUX_CENTRAL 1       /* arithmetic mean of the nodal fluxes                        */
 #define SBP_FLUX_KENNEDY_GRUBER 2 /* split form SF-KG                                          */
+#define SBP_FLUX_DC 3            /* standard DC: SBP derivative of the nodal fluxes, central   */
+                                 /* interface flux                                             */
 
 /* One periodic problem.  Constants follow the constituent relations of the compressible
  * Navier-Stokes section: P = rho R T, c_p = gamma R / (gamma - 1), constant viscosity mu and
@@ -63,7 +65,7 @@ typedef struct sbp_problem {
     const double *jac;      /* device [K*N^3]                                                  */
     double gamma, R, mu, Pr;
     double eta;             /* interior-penalty coefficient >= 0                               */
-    int32_t two_point;      /* SBP_FLUX_*                                                      */
+    int32_t two_point;      /* SBP_FLUX_*: inviscid volume form and interface flux            */
     int32_t reserved;       /* must be 0                                                       */
 } sbp_problem;
 

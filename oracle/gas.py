@@ -136,7 +136,10 @@ def central_flux(qi, qj, gas: Gas):
     return 0.5 * (euler_flux(qi, gas) + euler_flux(qj, gas))
 
 
-TWO_POINT = {0: chandrashekar_flux, 1: central_flux, 2: kennedy_gruber_flux}
+# Two-point fluxes by option: 0 Chandrashekar (ES-C), 1 central, 2 Kennedy-Gruber (SF-KG).
+# Option 3 is the standard DC discretization: its volume term is not a two-point form; its
+# interface flux is the central flux (plus the optional Lax-Friedrichs dissipation).
+TWO_POINT = {0: chandrashekar_flux, 1: central_flux, 2: kennedy_gruber_flux, 3: central_flux}
 
 
 def contract(F, n):

@@ -31,7 +31,8 @@ from .geometry import apply_D
 
 class Params:
     """Problem constants: the gas, interior-penalty coefficient eta, whether interface
-    dissipation is on, and the two-point flux (0 Chandrashekar, 1 central, 2 Kennedy-Gruber)."""
+    dissipation is on, and the inviscid volume form: 0 Chandrashekar (ES-C), 1 central, 2
+    Kennedy-Gruber (SF-KG) two-point fluxes, or 3 the standard DC form."""
 
     def __init__(self, gamma=1.4, R=1.0, mu=0.0, Pr=0.72, eta=1.0, iface_diss=1, two_point=0):
         self.gas = G.Gas(gamma, R, mu, Pr)
@@ -67,7 +68,13 @@ def _faces(p):
 
 def volume_term(q, metric, sbp, prm: Params):
     """sum_l sum_j D(i_l, j_l) (A_l,i + A_l,j) . F#(q_i, q_j) over the nodes j on the xi_l line
-    through i (eq. discEL), for element arrays q (5, n, N, N, N)."""
+    through i (eq. discEL), for element arrays q (5, n, N, N, N).
+
+    For the standard DC form (option 3) the SBP derivative is applied to the nodal inviscid fluxes
+    (eq. ns_iflux) in strong conservation form: sum_l D_l (sum_m [A_lm] F_m)."""
+    if prm.two_point == 3:
+        F = G.euler_flux(q, prm.gas)
+        return sum(apply_D(sbp.D, G.contract(F, metric[3 * l:3 * l + 3]), l) for l in range(3))
     flux = G.TWO_POINT[prm.two_point]
     V = np.zeros_like(q)
     N = sbp.N

@@ -136,7 +136,7 @@ int check_problem(const sbp_problem &pr) {
         return SBP_ERR_ARG;
     if (!(pr.gamma > 1.0) || !(pr.R > 0.0) || !(pr.mu >= 0.0) || !(pr.eta >= 0.0)) return SBP_ERR_ARG;
     if (pr.mu > 0.0 && !(pr.Pr > 0.0)) return SBP_ERR_ARG;
-    if (pr.two_point < 0 || pr.two_point > 2 || pr.reserved != 0) return SBP_ERR_ARG;
+    if (pr.two_point < 0 || pr.two_point > 3 || pr.reserved != 0) return SBP_ERR_ARG;
     if (pr.iface_diss != 0 && pr.iface_diss != 1) return SBP_ERR_ARG;
     return SBP_OK;
 }

@@ -82,8 +82,22 @@ __device__ __forceinline__ void primitives_nolog(const double q[5], double gm1, 
     n.lbeta = 0.0;
 }
 
+// Nodal inviscid flux (eq. ns_iflux) contracted with (n0, n1, n2): [rho U_n, rho U_n U + P n,
+// U_n (rho E + P)].
+__device__ __forceinline__ void euler_flux_n(const Node &a, double P, double rhoE, double n0,
+                                             double n1, double n2, double f[5]) {
+    const double un = a.u1 * n0 + a.u2 * n1 + a.u3 * n2;
+    const double m = a.rho * un;
+    f[0] = m;
+    f[1] = fma(m, a.u1, P * n0);
+    f[2] = fma(m, a.u2, P * n1);
+    f[3] = fma(m, a.u3, P * n2);
+    f[4] = un * (rhoE + P);
+}
+
 // Two-point flux F#(a, b) contracted with the vector (n0, n1, n2).
-// FLUX 0: Chandrashekar (entropy conservative), 1: central, 2: Kennedy-Gruber.
+// FLUX 0: Chandrashekar (entropy conservative), 1: central, 2: Kennedy-Gruber; 3 (standard DC)
+// uses the central flux at interfaces.
 // LAZY: b.lrho and b.lbeta are not set; they are computed only in the (rare) direct branch.
 template <int FLUX, bool LAZY = false>
 __device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, double n1, double n2,
@@ -116,7 +130,7 @@ __device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, 
     } else {
         // pressures and specific total energies from the staged node data
         const double Pa = 0.5 * a.rho / a.beta, Pb = 0.5 * b.rho / b.beta;
-        if constexpr (FLUX == 1) {
+        if constexpr (FLUX == 1 || FLUX == 3) {
             const double una = a.u1 * n0 + a.u2 * n1 + a.u3 * n2;
             const double unb = b.u1 * n0 + b.u2 * n1 + b.u3 * n2;
             const double ma = a.rho * una, mb = b.rho * unb;

@@ -76,70 +76,95 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     // (the j = i terms cancel exactly against the own-flux part of the interface SAT).  The metric
     // rows of consecutive directions and the mailboxes of consecutive rounds alternate between two
     // LDS areas, so one barrier per round suffices.
-    int round = 0;
+    if constexpr (FLUX == 3) {
+        // standard DC: -sum_l D_l (A_l . F) with the nodal fluxes, one direction at a time
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int fa = (l & 1) ? F_A1 : F_A0;
-        if (tid < NODES) {
-            s_buf[(fa + 0) * NODES + tid] = A[l][0];
-            s_buf[(fa + 1) * NODES + tid] = A[l][1];
-            s_buf[(fa + 2) * NODES + tid] = A[l][2];
-        }
-        __syncthreads();
-        const int il = idx[l];
-        const int st = stride[l];
-        auto pair = [&](int b, double f[5]) {
-            const int pn = tid + (b - il) * st;
-            Node o;
-            o.rho = s_buf[F_RHO * NODES + pn];
-            o.u1 = s_buf[F_U1 * NODES + pn];
-            o.u2 = s_buf[F_U2 * NODES + pn];
-            o.u3 = s_buf[F_U3 * NODES + pn];
-            o.beta = s_buf[F_B * NODES + pn];
-            o.lrho = s_buf[F_LR * NODES + pn];
-            o.lbeta = s_buf[F_LB * NODES + pn];
-            o.k = s_buf[F_K * NODES + pn];
-            const double n0 = A[l][0] + s_buf[(fa + 0) * NODES + pn];
-            const double n1 = A[l][1] + s_buf[(fa + 1) * NODES + pn];
-            const double n2 = A[l][2] + s_buf[(fa + 2) * NODES + pn];
-            flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
-            return pn;
-        };
-#pragma unroll
-        for (int r = 1; 2 * r < N; ++r) {
-            const int fm = (round & 1) ? F_MSG1 : F_MSG0;
-            ++round;
-            int b = il + r;
-            if (b >= N) b -= N;
+        for (int l = 0; l < 3; ++l) {
             if (tid < NODES) {
                 double f[5];
-                const int pn = pair(b, f);
-                const double dab = s_D[il * N + b], dba = s_D[b * N + il];
+                euler_flux_n(me, Pme, q[4], A[l][0], A[l][1], A[l][2], f);
 #pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    acc[c] = fma(-dab, f[c], acc[c]);
-                    s_buf[(fm + c) * NODES + pn] = dba * f[c];
-                }
+                for (int c = 0; c < 5; ++c) s_buf[(F_MSG0 + c) * NODES + tid] = f[c];
             }
             __syncthreads();
             if (tid < NODES) {
+                const int il = idx[l];
 #pragma unroll
-                for (int c = 0; c < 5; ++c) acc[c] -= s_buf[(fm + c) * NODES + tid];
+                for (int b = 0; b < N; ++b) {
+                    const double dd = s_D[il * N + b];
+                    const int pn = tid + (b - il) * stride[l];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[c] = fma(-dd, s_buf[(F_MSG0 + c) * NODES + pn], acc[c]);
+                }
             }
+            __syncthreads();
         }
-        if constexpr (N % 2 == 0) {
+    } else {
+        int round = 0;
+    #pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int fa = (l & 1) ? F_A1 : F_A0;
             if (tid < NODES) {
-                int b = il + N / 2;
+                s_buf[(fa + 0) * NODES + tid] = A[l][0];
+                s_buf[(fa + 1) * NODES + tid] = A[l][1];
+                s_buf[(fa + 2) * NODES + tid] = A[l][2];
+            }
+            __syncthreads();
+            const int il = idx[l];
+            const int st = stride[l];
+            auto pair = [&](int b, double f[5]) {
+                const int pn = tid + (b - il) * st;
+                Node o;
+                o.rho = s_buf[F_RHO * NODES + pn];
+                o.u1 = s_buf[F_U1 * NODES + pn];
+                o.u2 = s_buf[F_U2 * NODES + pn];
+                o.u3 = s_buf[F_U3 * NODES + pn];
+                o.beta = s_buf[F_B * NODES + pn];
+                o.lrho = s_buf[F_LR * NODES + pn];
+                o.lbeta = s_buf[F_LB * NODES + pn];
+                o.k = s_buf[F_K * NODES + pn];
+                const double n0 = A[l][0] + s_buf[(fa + 0) * NODES + pn];
+                const double n1 = A[l][1] + s_buf[(fa + 1) * NODES + pn];
+                const double n2 = A[l][2] + s_buf[(fa + 2) * NODES + pn];
+                flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
+                return pn;
+            };
+    #pragma unroll
+            for (int r = 1; 2 * r < N; ++r) {
+                const int fm = (round & 1) ? F_MSG1 : F_MSG0;
+                ++round;
+                int b = il + r;
                 if (b >= N) b -= N;
-                double f[5];
-                pair(b, f);
-                const double dab = s_D[il * N + b];
-#pragma unroll
-                for (int c = 0; c < 5; ++c) acc[c] = fma(-dab, f[c], acc[c]);
+                if (tid < NODES) {
+                    double f[5];
+                    const int pn = pair(b, f);
+                    const double dab = s_D[il * N + b], dba = s_D[b * N + il];
+    #pragma unroll
+                    for (int c = 0; c < 5; ++c) {
+                        acc[c] = fma(-dab, f[c], acc[c]);
+                        s_buf[(fm + c) * NODES + pn] = dba * f[c];
+                    }
+                }
+                __syncthreads();
+                if (tid < NODES) {
+    #pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[c] -= s_buf[(fm + c) * NODES + tid];
+                }
+            }
+            if constexpr (N % 2 == 0) {
+                if (tid < NODES) {
+                    int b = il + N / 2;
+                    if (b >= N) b -= N;
+                    double f[5];
+                    pair(b, f);
+                    const double dab = s_D[il * N + b];
+    #pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[c] = fma(-dab, f[c], acc[c]);
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     const double iJ = rcp(J);
     const double mu = a.mu, kap = a.kap;
@@ -200,6 +225,13 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                          n2 = 0.5 * (A[l][2] + An2);
             double f[5];
             flux_n<FLUX, true>(me, o, n0, n1, n2, gm1, f);
+            if constexpr (FLUX == 3) {
+                // no j = i volume term to cancel against: keep the own-flux part of the SAT
+                double fo[5];
+                euler_flux_n(me, Pme, q[4], A[l][0], A[l][1], A[l][2], fo);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) f[c] -= fo[c];
+            }
 #pragma unroll
             for (int c = 0; c < 5; ++c) acc[c] = fma(-s * isw, f[c], acc[c]);
             if (a.iface_diss) {
@@ -586,6 +618,7 @@ int launch_res_e(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
     switch (flux) {
         case 1: return visc ? launch_res_k<N, EPW, true, 1, false>(g, s) : launch_res_k<N, EPW, false, 1, false>(g, s);
         case 2: return visc ? launch_res_k<N, EPW, true, 2, false>(g, s) : launch_res_k<N, EPW, false, 2, false>(g, s);
+        case 3: return visc ? launch_res_k<N, EPW, true, 3, false>(g, s) : launch_res_k<N, EPW, false, 3, false>(g, s);
         default: return -1;
     }
 }

@@ -29,6 +29,11 @@ CASES = [
     (6, 2, 0.01, 1, 0, 0.1, 1.0),
     (7, 2, 0.02, 1, 0, 0.15, 1.0),
     (8, 2, 0.01, 1, 0, 0.1, 1.0),
+    (1, 3, 0.0, 1, 3, 0.1, 1.0),
+    (3, 3, 0.02, 1, 3, 0.12, 1.0),
+    (4, 2, 0.0, 0, 3, 0.1, 1.0),
+    (7, 2, 0.01, 1, 3, 0.1, 1.0),
+    (2, 3, 0.01, 1, 2, 0.1, 1.0),
 ]
 
 

@@ -241,3 +241,37 @@ def test_navier_stokes_residual_converges_to_continuous_rhs(A, min_rate):
         errs.append([np.abs(r[k] - ex[k]).max() for k in range(5)])
     rates = [math.log2(errs[0][k] / errs[1][k]) for k in range(5)]
     assert min(rates) > min_rate, (errs, rates)
+
+
+# ------------------------------------------------------------------------------------------ DC form
+def test_dc_volume_is_derivative_of_nodal_flux_on_affine_mesh():
+    """Standard DC: on an affine mesh, D applied to the nodal flux equals the central-flux
+    flux-differencing form (both are D_l(A_l . F) there)."""
+    c = Case(W.make_problem(p=3, E=2, L=2.0, A=0.0, seed=13, u_rms=0.3, two_point=3))
+    q = c.jumpy(0.02, 8)
+    V_dc = R.volume_term(q, c.metric, c.sbp, c.prm)
+    V_c = R.volume_term(q, c.metric, c.sbp, R.Params(two_point=1))
+    assert rel_err(V_dc, V_c) < 1e-12
+
+
+def test_dc_conservation_and_freestream():
+    c = Case(W.make_problem(p=3, E=3, L=2.0, A=0.1, mu=0.02, seed=14, u_rms=0.3, two_point=3))
+    r = c.residual(c.jumpy(0.02, 9))
+    wj = c.weights3d() * c.jac
+    tot = (wj * r).sum(axis=(1, 2, 3, 4))
+    mag = (wj * np.abs(r)).sum(axis=(1, 2, 3, 4))
+    assert np.all(np.abs(tot) < 1e-13 * mag.max())
+    cf = Case(W.make_problem(p=3, E=3, L=2.0, A=0.1, init="constant", two_point=3))
+    F = G.euler_flux(cf.q, cf.prm.gas)
+    scale = np.abs(F).max() * np.abs(cf.metric).max() * np.abs(cf.sbp.D).max() / cf.jac.min()
+    assert np.abs(cf.residual()).max() < 1e-13 * scale * 3
+
+
+@pytest.mark.slow
+def test_dc_converges_on_isentropic_vortex():
+    errs = []
+    for E in (6, 12):
+        prob = W.make_problem(p=4, E=E, L=12.0, A=0.05, mu=0.0, init="vortex", Ma=0.5,
+                              R=1.0 / (1.4 * 0.25), iface_diss=1, two_point=3)
+        errs.append(np.abs(Case(prob).residual()).max())
+    assert math.log2(errs[0] / errs[1]) > 2.5, errs
