@@ -12,7 +12,69 @@
 namespace sbp {
 namespace {
 
-constexpr int LDS_FIELDS = 24;  // doubles of LDS per node in the residual kernel
+// Doubles of LDS per node in the residual kernel: node data (8), two metric-row areas (6), two
+// mailboxes (10).  For N >= 6 the face slots of the interface work items (6 N^2 x 9 per element)
+// reuse the 16 fields after the node data.
+constexpr int LDS_FIELDS = 24;
+
+// Interface terms at one face node i of face (l, s) with partner node pg on the neighbour: the
+// EC shared flux replacing the own flux, the Lax-Friedrichs dissipation and, for viscous problems,
+// the interior penalty (v[0..4]) and the SAT^theta increment of theta_l (v[5..8]).
+template <int FLUX, bool VISC>
+__device__ __forceinline__ void face_terms(const ResArgs &a, const Node &mi, double Pi,
+                                           const double qi[5], const double Ai[3], double iJi,
+                                           long long pg, int l, double s, double v[9]) {
+    const long long nodes = a.nodes;
+    const double gm1 = a.gamma - 1.0, isw = a.isw;
+    double qn[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
+    const double An0 = a.metric[(3 * l + 0) * nodes + pg];
+    const double An1 = a.metric[(3 * l + 1) * nodes + pg];
+    const double An2 = a.metric[(3 * l + 2) * nodes + pg];
+    Node o;
+    double Pn;
+    primitives_nolog(qn, gm1, o, Pn);
+    const double n0 = 0.5 * (Ai[0] + An0), n1 = 0.5 * (Ai[1] + An1), n2 = 0.5 * (Ai[2] + An2);
+    double f[5];
+    flux_n<FLUX, true>(mi, o, n0, n1, n2, gm1, f);
+    if constexpr (FLUX == 3) {
+        // no j = i volume term to cancel against: keep the own-flux part of the SAT
+        double fo[5];
+        euler_flux_n(mi, Pi, qi[4], Ai[0], Ai[1], Ai[2], fo);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) f[c] -= fo[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = -s * isw * f[c];
+    if (a.iface_diss) {
+        const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double li = fabs(mi.u1 * n0 + mi.u2 * n1 + mi.u3 * n2) + sqrt(a.gamma * Pi / mi.rho) * nn;
+        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
+        const double cf = -0.5 * fmax(li, lo) * isw;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[c] = fma(cf, qi[c] - qn[c], v[c]);
+    }
+    if constexpr (VISC) {
+        const double iTi = 2.0 * a.R * mi.beta, iTn = 2.0 * a.R * o.beta;
+        const double wi[4] = {mi.u1 * iTi, mi.u2 * iTi, mi.u3 * iTi, -iTi};
+        const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
+        const double ct = 0.5 * s * isw;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[5 + c] = ct * (wn[c] - wi[c]);
+        if (a.eta != 0.0) {
+            const double iJn = rcp(a.jac[pg]);
+            double dw[4], pi_[4], pn_[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dw[c] = wi[c] - wn[c];
+            visc_flux_rank1(Ai[0], Ai[1], Ai[2], iJi, dw, mi.u1, mi.u2, mi.u3, rcp(iTi), a.mu, a.kap, pi_);
+            visc_flux_rank1(An0, An1, An2, iJn, dw, o.u1, o.u2, o.u3, rcp(iTn), a.mu, a.kap, pn_);
+            const double cf = -0.5 * a.eta * isw;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c + 1] = fma(cf, pi_[c] + pn_[c], v[c + 1]);
+        }
+    }
+}
 
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
 template <int N, int EPW, bool VISC, int FLUX>
@@ -167,13 +229,118 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     }
 
     const double iJ = rcp(J);
-    const double mu = a.mu, kap = a.kap;
-    double T = 1.0, w[4] = {0.0, 0.0, 0.0, 0.0}, th[3][4];
+
+    // ---- interface terms: EC interface flux, Lax-Friedrichs dissipation, SAT^theta, IP --------
+    int faces = 0;
+    double dth[3][4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dth[l][c] = 0.0;
+    if constexpr (N >= 6) {
+        // (face, face node) work items spread over all lanes: only 6/N of the nodes lie on a face
+        // of a given direction, so a per-node loop over directions would leave most lanes idle.
+        // Each item leaves its terms in an LDS face slot (over the metric/mailbox areas); each
+        // node then adds its (at most three) slots in direction order.  Node data staged for the
+        // pair loop are still in LDS; own q, metrics and J are re-read (cache-resident).
+        constexpr int NT = NT_OF(NODES);
+        constexpr int FACE_ITEMS = EPW * 6 * N2;
+        constexpr int NV = VISC ? 9 : 5;
+        static_assert(NV * 6 <= (LDS_FIELDS - 8) * N, "face slots exceed the LDS tile");
+        double *fsl = s_buf + 8 * NODES;  // [NV][FACE_ITEMS]
+        for (int it = tid; it < FACE_ITEMS; it += NT) {
+            const int es = it / (6 * N2);
+            const int rem = it - es * 6 * N2;
+            const int f = rem / N2, t = rem - f * N2;
+            const int l = f >> 1, side = f & 1;
+            const long long ee = ebase + es;
+            double v[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) v[c] = 0.0;
+            const long long nb = ee < a.K ? (long long)a.nbr[ee * 6 + f] : -1;
+            if (ee < a.K && (nb < 0 || nb >= a.K)) atomicOr(a.status, FLAG_MESH);
+            if (ee < a.K && nb >= 0 && nb < a.K) {
+                const int il = side ? N - 1 : 0;
+                const int ta = t % N, tb = t / N;
+                const int lno = l == 0 ? il + N * ta + N2 * tb
+                                       : (l == 1 ? ta + N * il + N2 * tb : ta + N * tb + N2 * il);
+                const int sl = l == 0 ? 1 : (l == 1 ? N : N2);
+                const int pl = es * N3 + lno;
+                const long long go = ee * N3 + lno;
+                const long long pg = nb * N3 + lno + (N - 1 - 2 * il) * sl;
+                double qi[5], Ai[3];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) Ai[m] = a.metric[(3 * l + m) * nodes + go];
+                Node mi;
+                mi.rho = s_buf[F_RHO * NODES + pl];
+                mi.u1 = s_buf[F_U1 * NODES + pl];
+                mi.u2 = s_buf[F_U2 * NODES + pl];
+                mi.u3 = s_buf[F_U3 * NODES + pl];
+                mi.beta = s_buf[F_B * NODES + pl];
+                mi.lrho = s_buf[F_LR * NODES + pl];
+                mi.lbeta = s_buf[F_LB * NODES + pl];
+                mi.k = s_buf[F_K * NODES + pl];
+                const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
+                const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
+                face_terms<FLUX, VISC>(a, mi, Pi, qi, Ai, iJi, pg, l, side ? 1.0 : -1.0, v);
+            }
+#pragma unroll
+            for (int c = 0; c < NV; ++c) fsl[c * FACE_ITEMS + it] = v[c];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int il = idx[l];
+                if (il != 0 && il != N - 1) continue;
+                const int side = (il == N - 1) ? 1 : 0;
+                const long long nb = a.nbr[e * 6 + 2 * l + side];
+                if (nb < 0 || nb >= a.K) continue;
+                faces |= 1 << l;
+                const int it = (slot * 6 + 2 * l + side) * N2 + tangential_index<N>(l, i1, i2, i3);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] += fsl[c * FACE_ITEMS + it];
+                if constexpr (VISC) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dth[l][c] = fsl[(5 + c) * FACE_ITEMS + it];
+                }
+            }
+        }
+    } else {
+        // small elements: most nodes lie on faces, so each node walks its own faces
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int il = idx[l];
+                if (il != 0 && il != N - 1) continue;
+                const int side = (il == N - 1) ? 1 : 0;
+                const long long nb = a.nbr[e * 6 + 2 * l + side];
+                if (nb < 0 || nb >= a.K) {
+                    atomicOr(a.status, FLAG_MESH);
+                    continue;
+                }
+                faces |= 1 << l;
+                const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
+                double v[9];
+                face_terms<FLUX, VISC>(a, me, Pme, q, A[l], iJ, pg, l, side ? 1.0 : -1.0, v);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] += v[c];
+                if constexpr (VISC) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dth[l][c] = v[5 + c];
+                }
+            }
+        }
+    }
+
+    double T = 1.0, th[3][4];
     if constexpr (VISC) {
         // ---- BR1 gradient theta_a = D_a w from the lines (w = (U/T, -1/T); W_1 is not needed) --
         const double iT = 2.0 * a.R * me.beta;
         T = rcp(iT);
-        w[0] = me.u1 * iT; w[1] = me.u2 * iT; w[2] = me.u3 * iT; w[3] = -iT;
+        const double w[4] = {me.u1 * iT, me.u2 * iT, me.u3 * iT, -iT};
         if (tid < NODES) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) s_buf[c * NODES + tid] = w[c];
@@ -182,7 +349,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) th[d][c] = 0.0;
+            for (int c = 0; c < 4; ++c) th[d][c] = dth[d][c];
             if (tid < NODES) {
                 const int il = idx[d];
 #pragma unroll
@@ -191,76 +358,6 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     const int pn = tid + (b - il) * stride[d];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) th[d][c] = fma(dd, s_buf[c * NODES + pn], th[d][c]);
-                }
-            }
-        }
-    }
-
-    // ---- faces: EC interface flux, Lax-Friedrichs dissipation, SAT^theta, interior penalty ----
-    int faces = 0;
-    if (active) {
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int il = idx[l];
-            if (il != 0 && il != N - 1) continue;
-            const int side = (il == N - 1) ? 1 : 0;
-            const double s = side ? 1.0 : -1.0;
-            const long long nb = a.nbr[e * 6 + 2 * l + side];
-            if (nb < 0 || nb >= a.K) {
-                atomicOr(a.status, FLAG_MESH);
-                continue;
-            }
-            faces |= 1 << l;
-            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
-            double qn[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
-            const double An0 = a.metric[(3 * l + 0) * nodes + pg];
-            const double An1 = a.metric[(3 * l + 1) * nodes + pg];
-            const double An2 = a.metric[(3 * l + 2) * nodes + pg];
-            Node o;
-            double Pn;
-            primitives_nolog(qn, gm1, o, Pn);
-            const double n0 = 0.5 * (A[l][0] + An0), n1 = 0.5 * (A[l][1] + An1),
-                         n2 = 0.5 * (A[l][2] + An2);
-            double f[5];
-            flux_n<FLUX, true>(me, o, n0, n1, n2, gm1, f);
-            if constexpr (FLUX == 3) {
-                // no j = i volume term to cancel against: keep the own-flux part of the SAT
-                double fo[5];
-                euler_flux_n(me, Pme, q[4], A[l][0], A[l][1], A[l][2], fo);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) f[c] -= fo[c];
-            }
-#pragma unroll
-            for (int c = 0; c < 5; ++c) acc[c] = fma(-s * isw, f[c], acc[c]);
-            if (a.iface_diss) {
-                const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-                const double li = fabs(me.u1 * n0 + me.u2 * n1 + me.u3 * n2) +
-                                  sqrt(a.gamma * Pme / me.rho) * nn;
-                const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) +
-                                  sqrt(a.gamma * Pn / o.rho) * nn;
-                const double cf = -0.5 * fmax(li, lo) * isw;
-#pragma unroll
-                for (int c = 0; c < 5; ++c) acc[c] = fma(cf, q[c] - qn[c], acc[c]);
-            }
-            if constexpr (VISC) {
-                const double iTn = 2.0 * a.R * o.beta;
-                const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
-                const double ct = 0.5 * s * isw;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) th[l][c] = fma(ct, wn[c] - w[c], th[l][c]);
-                if (a.eta != 0.0) {
-                    const double iJn = rcp(a.jac[pg]);
-                    double dw[4], pi_[4], pn_[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) dw[c] = w[c] - wn[c];
-                    visc_flux_rank1(A[l][0], A[l][1], A[l][2], iJ, dw, me.u1, me.u2, me.u3, T, mu,
-                                    kap, pi_);
-                    visc_flux_rank1(An0, An1, An2, iJn, dw, o.u1, o.u2, o.u3, rcp(iTn), mu, kap, pn_);
-                    const double cf = -0.5 * a.eta * isw;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cf, pi_[c] + pn_[c], acc[c + 1]);
                 }
             }
         }
@@ -275,7 +372,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             for (int c = 0; c < 4; ++c)
                 gr[j][c] = (A[0][j] * th[0][c] + A[1][j] * th[1][c] + A[2][j] * th[2][c]) * iJ;
         double FV[3][4];
-        visc_flux_full(gr, me.u1, me.u2, me.u3, T, mu, kap, FV);
+        visc_flux_full(gr, me.u1, me.u2, me.u3, T, a.mu, a.kap, FV);
         double fh[3][4];
 #pragma unroll
         for (int l = 0; l < 3; ++l)

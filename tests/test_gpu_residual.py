@@ -34,6 +34,10 @@ CASES = [
     (4, 2, 0.0, 0, 3, 0.1, 1.0),
     (7, 2, 0.01, 1, 3, 0.1, 1.0),
     (2, 3, 0.01, 1, 2, 0.1, 1.0),
+    (5, 2, 0.02, 1, 0, 0.1, 0.0),
+    (6, 2, 0.0, 0, 2, 0.1, 1.0),
+    (8, 2, 0.0, 1, 1, 0.12, 1.0),
+    (6, 2, 0.01, 0, 0, 0.1, 1.0),
 ]
 
 
