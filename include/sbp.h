@@ -45,7 +45,10 @@ extern "C" {
 #define SBP_ERR_HIP (-5)         /* a HIP runtime call failed                                  */
 #define SBP_ERR_WORKSPACE (-6)   /* workspace missing or smaller than sbp_workspace_bytes()    */
 
-#define SBP_MAX_P 8
+#define SBP_MAX_P 15      /* degrees 1..8 run one workgroup per element tile; 9..15 (the cost */
+                         /* study of the Taylor-Green section goes up to p = 15) run as      */
+                         /* passes over node planes                                          */
+#define SBP_MAX_VJP_P 8  /* sbp_residual_vjp covers degrees 1..8                             */
 
 #define SBP_FLUX_CHANDRASHEKAR 0 /* entropy-conservative two-point flux (ES-C)                 */
 #define SBP_FLUX_CENTRAL 1       /* arithmetic mean of the nodal fluxes                        */
@@ -112,20 +115,21 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
  * element recomputing its forward intermediates (no two-point fluxes are stored) and interface
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
  * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0); other fluxes give
- * SBP_ERR_ARG.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
+ * SBP_ERR_ARG, degrees above SBP_MAX_VJP_P give SBP_ERR_DEGREE.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
  * in the interface dissipation takes the own side on ties. */
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
                      double *qbar, void *ws, size_t ws_bytes, void *stream);
 
 /* Profiling variant of sbp_residual for one problem (n_prob == 1): the same launches, with HIP
- * events recorded on `stream` around the main residual kernel; waits for the end event and stores
+ * events recorded on `stream` around the main residual kernel (around all plane passes for
+ * p > 8); waits for the end event and stores
  * that kernel's duration in *kernel_ms (host pointer).  Not for use under graph capture. */
 int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
                          void *ws, size_t ws_bytes, void *stream, float *kernel_ms);
 
 /* Autotuner: for each group of problems sharing degree, viscosity on/off and flux, times every
- * schedule of the residual kernel (elements per workgroup; one block per element tile or a
- * persistent grid) on these inputs, `reps` launches each after a warm-up, and keeps the fastest for
+ * schedule of the residual kernel (elements per workgroup, one block per element tile or a
+ * persistent grid; node planes per workgroup for p > 8) on these inputs, `reps` launches each after a warm-up, and keeps the fastest for
  * later calls with the same problem array and workspace.  Waits for `stream`.  dqdt is scratch
  * output.  chosen: optional host [n_prob] receiving the schedule index of each problem's group. */
 int sbp_autotune(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt, void *ws,

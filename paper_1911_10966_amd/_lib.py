@@ -13,7 +13,8 @@ SBP_ERR_MESH = -3
 SBP_ERR_NONPHYSICAL = -4
 SBP_ERR_HIP = -5
 SBP_ERR_WORKSPACE = -6
-SBP_MAX_P = 8
+SBP_MAX_P = 15
+SBP_MAX_VJP_P = 8
 
 EXPORTED = ("sbp_version", "sbp_error_string", "sbp_lgl_operator", "sbp_metrics",
             "sbp_workspace_bytes", "sbp_residual", "sbp_rk_step", "sbp_residual_vjp",

@@ -168,8 +168,10 @@ Layout layout_of(const sbp_problem *probs, int n) {
         if (probs[b].mu > 0.0) {
             L.trace[b] = off;
             off += align_up(sizeof(double) * (size_t)probs[b].n_elem * 6 * 4 * N * N);
+            // VJP gradient cotangents (12 per node) or the plane passes' scratch (16 per node)
             L.thb[b] = off;
-            off += align_up(sizeof(double) * 12 * (size_t)nodes_of(probs[b]));
+            const size_t per = probs[b].p >= sbp::kFirstPlaneP ? 16 : 12;
+            off += align_up(sizeof(double) * per * (size_t)nodes_of(probs[b]));
         }
         states += 5 * (size_t)nodes_of(probs[b]);
     }
@@ -297,8 +299,11 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
         for (int v = 0; v < sbp::schedule_count(g.p); ++v) {
             const int epw = sbp::schedule_of(g.p, v).epw;
             if (g.d_block_start.count(epw)) continue;
+            // work units: elements, or node planes (N per element) for the plane passes
+            const long long per_elem = g.p >= sbp::kFirstPlaneP ? g.p + 1 : 1;
             std::vector<long long> bs(1, 0);
-            for (int b : g.members) bs.push_back(bs.back() + (probs[b].n_elem + epw - 1) / epw);
+            for (int b : g.members)
+                bs.push_back(bs.back() + (probs[b].n_elem * per_elem + epw - 1) / epw);
             g.d_block_start[epw] = to_device(bs);
             g.total_blocks[epw] = bs.back();
             if (!g.d_block_start[epw]) return nullptr;
@@ -444,7 +449,7 @@ int sbp_lgl_operator(int32_t p, double *x, double *w, double *D) {
 
 int sbp_metrics(int32_t p, int64_t n_elem, const double *coords, double *metric, double *jac,
                 void *stream) {
-    if (p < 1 || p > 9) return SBP_ERR_DEGREE;
+    if (p < 1 || p > SBP_MAX_P) return SBP_ERR_DEGREE;
     if (n_elem <= 0 || !aligned8(coords) || !aligned8(metric) || !aligned8(jac)) return SBP_ERR_ARG;
     const double *D = device_D(p);
     if (!D) return SBP_ERR_HIP;
@@ -511,8 +516,10 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     if (rc != SBP_OK) return rc;
     if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
         return SBP_ERR_ARG;
-    for (int b = 0; b < n_prob; ++b)
+    for (int b = 0; b < n_prob; ++b) {
         if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR) return SBP_ERR_ARG;
+        if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
+    }
     char *w = static_cast<char *>(ws);
     size_t off = 0;
     for (int b = 0; b < n_prob; ++b) {

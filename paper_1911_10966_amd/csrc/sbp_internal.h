@@ -1,5 +1,5 @@
 // Internal declarations shared by the C-ABI layer (sbp_capi.cpp) and the gfx950 kernels
-// (sbp_kernels.hip).  Not part of the public interface.
+// (sbp_kernels.hip, sbp_planes.hip, sbp_vjp.hip).  Not part of the public interface.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +17,7 @@ struct ResArgs {
     const double *jac;     // [nodes]
     const int32_t *nbr;    // [K][6]
     double *trace;         // viscous face traces [K][6][4][N^2] (mu > 0 only)
+    double *aux;           // viscous per-node scratch of the plane kernels, [16][nodes] (mu > 0 only)
     int *status;           // sticky flags
     const double *D;       // [N*N] collocation derivative
     long long K;
@@ -85,6 +86,12 @@ Schedule schedule_of(int p, int variant);
 int launch_group_residual(int p, bool visc, int flux, int variant, const GroupArgs &g, hipStream_t s,
                           bool fixup);
 int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArgs &r, hipStream_t s);
+// Degrees whose elements exceed one workgroup (p >= 9) run as passes over node planes; a
+// schedule's `epw` is then the number of planes per workgroup.
+constexpr int kFirstPlaneP = 9;
+int launch_group_residual_planes(int p, int ppb, bool visc, int flux, const GroupArgs &g, hipStream_t s);
+int launch_metrics_big(int p, long long K, const double *x, double *metric, double *jac,
+                       const double *D, hipStream_t s);
 
 // RK4 stage update, see launch_rk_stage.
 struct RkArgs {

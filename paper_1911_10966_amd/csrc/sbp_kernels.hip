@@ -17,65 +17,6 @@ namespace {
 // reuse the 16 fields after the node data.
 constexpr int LDS_FIELDS = 24;
 
-// Interface terms at one face node i of face (l, s) with partner node pg on the neighbour: the
-// EC shared flux replacing the own flux, the Lax-Friedrichs dissipation and, for viscous problems,
-// the interior penalty (v[0..4]) and the SAT^theta increment of theta_l (v[5..8]).
-template <int FLUX, bool VISC>
-__device__ __forceinline__ void face_terms(const ResArgs &a, const Node &mi, double Pi,
-                                           const double qi[5], const double Ai[3], double iJi,
-                                           long long pg, int l, double s, double v[9]) {
-    const long long nodes = a.nodes;
-    const double gm1 = a.gamma - 1.0, isw = a.isw;
-    double qn[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
-    const double An0 = a.metric[(3 * l + 0) * nodes + pg];
-    const double An1 = a.metric[(3 * l + 1) * nodes + pg];
-    const double An2 = a.metric[(3 * l + 2) * nodes + pg];
-    Node o;
-    double Pn;
-    primitives_nolog(qn, gm1, o, Pn);
-    const double n0 = 0.5 * (Ai[0] + An0), n1 = 0.5 * (Ai[1] + An1), n2 = 0.5 * (Ai[2] + An2);
-    double f[5];
-    flux_n<FLUX, true>(mi, o, n0, n1, n2, gm1, f);
-    if constexpr (FLUX == 3) {
-        // no j = i volume term to cancel against: keep the own-flux part of the SAT
-        double fo[5];
-        euler_flux_n(mi, Pi, qi[4], Ai[0], Ai[1], Ai[2], fo);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) f[c] -= fo[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) v[c] = -s * isw * f[c];
-    if (a.iface_diss) {
-        const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-        const double li = fabs(mi.u1 * n0 + mi.u2 * n1 + mi.u3 * n2) + sqrt(a.gamma * Pi / mi.rho) * nn;
-        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
-        const double cf = -0.5 * fmax(li, lo) * isw;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v[c] = fma(cf, qi[c] - qn[c], v[c]);
-    }
-    if constexpr (VISC) {
-        const double iTi = 2.0 * a.R * mi.beta, iTn = 2.0 * a.R * o.beta;
-        const double wi[4] = {mi.u1 * iTi, mi.u2 * iTi, mi.u3 * iTi, -iTi};
-        const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
-        const double ct = 0.5 * s * isw;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[5 + c] = ct * (wn[c] - wi[c]);
-        if (a.eta != 0.0) {
-            const double iJn = rcp(a.jac[pg]);
-            double dw[4], pi_[4], pn_[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) dw[c] = wi[c] - wn[c];
-            visc_flux_rank1(Ai[0], Ai[1], Ai[2], iJi, dw, mi.u1, mi.u2, mi.u3, rcp(iTi), a.mu, a.kap, pi_);
-            visc_flux_rank1(An0, An1, An2, iJn, dw, o.u1, o.u2, o.u3, rcp(iTn), a.mu, a.kap, pn_);
-            const double cf = -0.5 * a.eta * isw;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c + 1] = fma(cf, pi_[c] + pn_[c], v[c + 1]);
-        }
-    }
-}
-
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
 template <int N, int EPW, bool VISC, int FLUX>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
@@ -423,41 +364,6 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     }
 }
 
-__device__ __forceinline__ int find_problem(const long long *start, int n, long long v) {
-    int lo = 0, hi = n;  // start[lo] <= v < start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= v) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDev &P, double *out) {
-    ResArgs a;
-    a.q = g.q + P.off;
-    a.out = out + P.off;
-    a.metric = P.metric;
-    a.jac = P.jac;
-    a.nbr = P.nbr;
-    a.trace = P.trace;
-    a.status = g.status;
-    a.D = g.D;
-    a.K = P.K;
-    a.nodes = P.nodes;
-    a.gamma = P.gamma;
-    a.R = P.R;
-    a.mu = P.mu;
-    a.Pr = P.Pr;
-    a.eta = P.eta;
-    a.w_end = P.w_end;
-    a.isw = P.isw;
-    a.kap = P.kap;
-    a.iface_diss = P.iface_diss;
-    a.two_point = P.two_point;
-    return a;
-}
-
 // Residual over a group of problems.  Non-persistent: one block per element tile.  Persistent:
 // a grid sized to the resident capacity walks the tiles (the grid is a multiple of the XCD count,
 // so the XCD-contiguous remap of tile indices still holds).
@@ -668,6 +574,7 @@ constexpr Schedule kSched3[] = {{2, 0, 0}, {7, 0, 0}, {2, 1, 0}, {7, 1, 0}, {7, 
 constexpr Schedule kSched4[] = {{1, 0, 0}, {2, 0, 0}, {4, 0, 0}, {1, 1, 0}, {2, 1, 0}, {1, 0, 4}, {2, 0, 4}};
 constexpr Schedule kSched5[] = {{1, 0, 0}, {2, 0, 0}, {1, 1, 0}, {2, 1, 0}, {1, 0, 4}, {2, 0, 4}, {1, 0, 3}};
 constexpr Schedule kSchedBig[] = {{1, 0, 0}, {1, 1, 0}, {1, 0, 4}, {1, 0, 3}};
+constexpr Schedule kSchedPlanes[] = {{1, 0, 0}, {2, 0, 0}};  // planes per workgroup
 
 int device_cus() {
     static int cus = 0;
@@ -750,6 +657,8 @@ int schedule_count(int p) {
         case 3: return (int)(sizeof(kSched4) / sizeof(Schedule));
         case 4: return (int)(sizeof(kSched5) / sizeof(Schedule));
         case 5: case 6: case 7: case 8: return (int)(sizeof(kSchedBig) / sizeof(Schedule));
+        case 9: case 10: case 11: case 12: case 13: case 14: case 15:
+            return (int)(sizeof(kSchedPlanes) / sizeof(Schedule));
         default: return 0;
     }
 }
@@ -760,7 +669,7 @@ Schedule schedule_of(int p, int v) {
         case 2: return kSched3[v];
         case 3: return kSched4[v];
         case 4: return kSched5[v];
-        default: return kSchedBig[v];
+        default: return p >= kFirstPlaneP ? kSchedPlanes[v] : kSchedBig[v];
     }
 }
 
@@ -769,6 +678,8 @@ int launch_group_residual(int p, bool visc, int flux, int variant, const GroupAr
     if (variant < 0 || variant >= schedule_count(p)) return -1;
     if (flux != 0 && variant != 0) return -1;
     const Schedule sc = schedule_of(p, variant);
+    // high degrees: plane passes, which finish SAT^V themselves (no fixup)
+    if (p >= kFirstPlaneP) return launch_group_residual_planes(p, sc.epw, visc, flux, g, s);
     int rc = -1;
     const bool P1 = sc.persistent != 0;
     if (flux == 0) {
@@ -830,6 +741,9 @@ int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArg
         case 6: return launch_rkg<7>(visc, g, r, s);
         case 7: return launch_rkg<8>(visc, g, r, s);
         case 8: return launch_rkg<9>(visc, g, r, s);
+        // plane passes leave a finished dq/dt: the stage kernel adds no SAT^V half
+        case 9: case 10: case 11: case 12: case 13: case 14: case 15:
+            return launch_rkg<2>(false, g, r, s);
         default: return -1;
     }
 }
@@ -862,6 +776,8 @@ int launch_metrics(int p, long long K, const double *x, double *metric, double *
         case 7: SBP_MET(8)
         case 8: SBP_MET(9)
         case 9: SBP_MET(10)
+        case 10: case 11: case 12: case 13: case 14: case 15:
+            return launch_metrics_big(p, K, x, metric, jac, D, s);
         default: return -1;
     }
 #undef SBP_MET

@@ -50,9 +50,15 @@ def test_argument_errors_on_host():
     pr = _lib.sbp_problem(3, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0)
     arr = (_lib.sbp_problem * 1)(pr)
     assert L.sbp_workspace_bytes(arr, 1) > 0
-    bad = (_lib.sbp_problem * 1)(_lib.sbp_problem(9, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0))
+    bad = (_lib.sbp_problem * 1)(_lib.sbp_problem(_lib.SBP_MAX_P + 1, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72,
+                                                  1.0, 0, 0))
     assert L.sbp_workspace_bytes(bad, 1) == 0
     assert L.sbp_residual(bad, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_DEGREE
+    # degrees above the VJP's range (the residual itself accepts them)
+    hi = (_lib.sbp_problem * 1)(_lib.sbp_problem(_lib.SBP_MAX_VJP_P + 1, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72,
+                                                 1.0, 0, 0))
+    assert L.sbp_workspace_bytes(hi, 1) > 0
+    assert L.sbp_residual_vjp(hi, 1, 64, 128, 192, 256, 1 << 22, None) == _lib.SBP_ERR_DEGREE
     # workspace too small
     assert L.sbp_residual(arr, 1, 64, 128, 256, 8, None) == _lib.SBP_ERR_WORKSPACE
     # aliasing output

@@ -38,6 +38,15 @@ CASES = [
     (6, 2, 0.0, 0, 2, 0.1, 1.0),
     (8, 2, 0.0, 1, 1, 0.12, 1.0),
     (6, 2, 0.01, 0, 0, 0.1, 1.0),
+    # degrees 9..15 run as plane passes
+    (9, 2, 0.01, 1, 0, 0.1, 1.0),
+    (10, 3, 0.0, 1, 0, 0.12, 1.0),
+    (11, 2, 0.02, 0, 2, 0.1, 1.0),
+    (12, 2, 0.01, 1, 3, 0.1, 1.0),
+    (13, 2, 0.0, 1, 1, 0.1, 1.0),
+    (14, 2, 0.01, 1, 0, 0.1, 0.0),
+    (15, 2, 0.01, 1, 0, 0.1, 1.0),
+    (15, 2, 0.0, 0, 3, 0.1, 1.0),
 ]
 
 
@@ -104,7 +113,8 @@ def test_bad_neighbour_is_flagged_not_read():
 
 def test_metrics_match_oracle():
     require_gpu()
-    for p, E, A in [(3, 3, 0.1), (4, 2, 0.15), (8, 2, 0.1), (1, 3, 0.1)]:
+    for p, E, A in [(3, 3, 0.1), (4, 2, 0.15), (8, 2, 0.1), (1, 3, 0.1), (9, 2, 0.1), (11, 2, 0.15),
+                    (15, 2, 0.1)]:
         c = Case(W.make_problem(p=p, E=E, L=2.0, A=A))
         x = torch.as_tensor(np.ascontiguousarray(c.x.reshape(3, -1)), device=DEV)
         m, j = P.metrics(p, x)
