@@ -237,7 +237,7 @@ def batched_rate(P, W, dev, steps, loop_baseline=True):
 
 def cost_experiment(P, W, dev, steps):
     """The paper's cost-of-entropy-stability test on one MI355X: Taylor-Green vortex (Re = 1600,
-    Ma = 0.05, periodic box of side 2 pi, Cartesian elements) at 256^3 DOFs for p = 1, 3, 7 with the
+    Ma = 0.05, periodic box of side 2 pi, Cartesian elements) at 256^3 DOFs for p = 1, 3, 7, 15 with the
     ES-C (Chandrashekar), SF-KG (Kennedy-Gruber) and DC volume terms; time per residual and per
     classical RK4 step.  The paper's figures (64 Haswell cores, DOPRI5 steps) are quoted as
     context."""
@@ -245,9 +245,10 @@ def cost_experiment(P, W, dev, steps):
     import torch
     paper = {1: {"ES-C": 3.1798, "SF-KG": 2.8634, "DC": 2.7771},
              3: {"ES-C": 2.5059, "SF-KG": 2.01675, "DC": 1.9593},
-             7: {"ES-C": 2.6099, "SF-KG": 1.73415, "DC": 1.5335}}
+             7: {"ES-C": 2.6099, "SF-KG": 1.73415, "DC": 1.5335},
+             15: {"ES-C": 3.5589, "SF-KG": 1.9914, "DC": 1.4830}}
     out = {"dofs": 256 ** 3, "box": "2pi periodic, Cartesian", "Ma": 0.05, "Re": 1600, "results": []}
-    for p in (1, 3, 7):
+    for p in (1, 3, 7, 15):
         E = 256 // (p + 1)
         for name, tp in (("ES-C", 0), ("SF-KG", 2), ("DC", 3)):
             Ma = 0.05
