@@ -273,6 +273,94 @@ def cost_experiment(P, W, dev, steps):
     return out
 
 
+def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=2000):
+    """The paper's robustness study of the Taylor-Green vortex (Re = 1600, Ma = 0.05, Cartesian
+    periodic box of side 2 pi, t_f = 20): for each mesh of E^3 elements and degree p, the ES-C,
+    SF-KG and DC discretizations are advanced together as one batched problem set (three graph
+    branches) with classical RK4 at dt = cfl (L/E) / ((p+1)^2 max(|U| + c)).  A run has failed when
+    its state holds a non-finite value or a non-positive density or pressure; failed runs leave the
+    set.  Reports, per run, success or the time of failure and, for runs that reach t_f, the
+    kinetic energy relative to its initial value."""
+    import math
+    import torch
+    Ma = 0.05
+    schemes = (("ES-C", 0), ("SF-KG", 2), ("DC", 3))
+    out = {"t_final": t_final, "cfl": cfl, "Ma": Ma, "Re": 1600, "integrator": "classical RK4, fixed dt",
+           "results": []}
+    t_start = time.time()
+    for E in meshes:
+        for p in degrees:
+            if time.time() - t_start > budget_s:
+                for name, _ in schemes:
+                    out["results"].append({"E": E, "p": p, "scheme": name, "result": "not run (time budget)"})
+                continue
+            probs = [W.make_problem(name=f"tgv_robust_p{p}_e{E}", p=p, E=E, L=2.0 * math.pi, A=0.0,
+                                    gamma=1.4, R=1.0 / (1.4 * Ma * Ma), mu=1.0 / 1600.0, Pr=0.72,
+                                    init="tgv", Ma=Ma, two_point=tp) for _, tp in schemes]
+            built = [device_problem(P, W, pr, dev) for pr in probs]
+            dt0 = built[0][2] * (cfl / 0.25)   # device_problem uses cfl 0.25
+            n_total = int(math.ceil(t_final / dt0))
+            dt = t_final / n_total
+            _, w, _ = P.lgl_operator(p)
+            wt = torch.as_tensor(w, dtype=torch.float64, device=dev)
+            w3 = (wt[None, None, :, None, None] * wt[None, None, None, :, None] * wt[None, None, None, None, :])
+            wJ = (w3.reshape(1, 1, -1) * built[0][0].jac.reshape(probs[0].K, -1)[None]).reshape(-1)
+
+            def kinetic(qq):
+                q5 = qq.reshape(5, -1)
+                return float(((0.5 * (q5[1] ** 2 + q5[2] ** 2 + q5[3] ** 2) / q5[0]) * wJ).sum() / wJ.sum())
+
+            def healthy(qq):
+                q5 = qq.reshape(5, -1)
+                pr_ = (1.4 - 1.0) * (q5[4] - 0.5 * (q5[1] ** 2 + q5[2] ** 2 + q5[3] ** 2) / q5[0])
+                return bool(torch.isfinite(q5).all()) and bool((q5[0] > 0).all()) and bool((pr_ > 0).all())
+
+            qs = [b[1].reshape(-1).clone() for b in built]
+            ek0 = kinetic(qs[0])
+            alive = [0, 1, 2]
+            fail = {}
+            done = 0
+            t0 = time.time()
+            ps, qcat, key = None, None, None
+            while done < n_total and alive:
+                if key != tuple(alive):
+                    key = tuple(alive)
+                    ps = P.ProblemSet([built[i][0] for i in alive])
+                    qcat = torch.cat([qs[i] for i in alive])
+                    dts = torch.full((len(alive),), dt, dtype=torch.float64, device=dev)
+                n = min(chunk, n_total - done)
+                ps.rk_step(qcat, dts, n)
+                try:
+                    ps.status()
+                except P.SBPError:
+                    pass
+                done += n
+                off = 0
+                for i in list(alive):
+                    m = qs[i].numel()
+                    qs[i] = qcat[off:off + m]
+                    off += m
+                    if not healthy(qs[i]):
+                        fail[i] = done * dt
+                for i in fail:
+                    if i in alive:
+                        alive.remove(i)
+                        qs[i] = qs[i].clone()
+            secs = time.time() - t0
+            for i, (name, _) in enumerate(schemes):
+                r = {"E": E, "p": p, "scheme": name, "steps": n_total, "dt": dt}
+                if i in fail:
+                    r.update(result="failure", t_fail_before=round(fail[i], 4))
+                else:
+                    r.update(result="success", kinetic_energy_ratio=round(kinetic(qs[i]) / ek0, 5))
+                out["results"].append(r)
+            print(f"robustness E={E} p={p}: steps {n_total}, {secs:.1f} s, failed "
+                  f"{[schemes[i][0] for i in sorted(fail)]}", file=sys.stderr, flush=True)
+            del ps, qcat, built, qs
+            torch.cuda.empty_cache()
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -286,6 +374,13 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--cost-experiment", action="store_true",
                     help="run only the ES-C / SF-KG / DC cost comparison at 256^3 DOFs and print it")
+    ap.add_argument("--robustness", action="store_true",
+                    help="run only the Taylor-Green robustness study (ES-C / SF-KG / DC to t = 20)")
+    ap.add_argument("--robust-meshes", default="3", help="comma-separated E of the E^3 meshes")
+    ap.add_argument("--robust-degrees", default="1-15", help="degrees, e.g. 1-15 or 1,3,7")
+    ap.add_argument("--robust-t-final", type=float, default=20.0)
+    ap.add_argument("--robust-cfl", type=float, default=0.5)
+    ap.add_argument("--robust-budget", type=float, default=900.0, help="seconds before skipping runs")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the plain/batched/VJP secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +405,17 @@ def main():
     torch.cuda.set_device(0)
     if args.cost_experiment:
         print(json.dumps({"cost_of_entropy_stability": cost_experiment(P, W, dev, 5)}), flush=True)
+        return 0
+    if args.robustness:
+        def int_list(spec):
+            vals = []
+            for part in spec.split(","):
+                a, _, b = part.partition("-")
+                vals += list(range(int(a), int(b) + 1)) if b else [int(a)]
+            return vals
+        res = tgv_robustness(P, W, dev, int_list(args.robust_meshes), int_list(args.robust_degrees),
+                             args.robust_t_final, args.robust_cfl, args.robust_budget)
+        print(json.dumps({"tgv_robustness": res}), flush=True)
         return 0
     prob = W.config(args.workload)
     dp, q, dt0 = device_problem(P, W, prob, dev)
