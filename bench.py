@@ -335,6 +335,8 @@ def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=200
                 except P.SBPError:
                     pass
                 done += n
+                if done % (10 * chunk) == 0:
+                    print(f"robustness E={E} p={p}: step {done}/{n_total}", file=sys.stderr, flush=True)
                 off = 0
                 for i in list(alive):
                     m = qs[i].numel()
@@ -356,6 +358,8 @@ def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=200
                 out["results"].append(r)
             print(f"robustness E={E} p={p}: steps {n_total}, {secs:.1f} s, failed "
                   f"{[schemes[i][0] for i in sorted(fail)]}", file=sys.stderr, flush=True)
+            print(json.dumps({"tgv_robustness_run": out["results"][-len(schemes):]}), file=sys.stderr,
+                  flush=True)
             del ps, qcat, built, qs
             torch.cuda.empty_cache()
     return out

@@ -275,21 +275,55 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
     return a;
 }
 
-// Interface terms at one face node i of face (l, s) with partner node pg on the neighbour: the
-// EC shared flux replacing the own flux, the Lax-Friedrichs dissipation and, for viscous problems,
-// the interior penalty (v[0..4]) and the SAT^theta increment of theta_l (v[5..8]).
-template <int FLUX, bool VISC>
-__device__ __forceinline__ void face_terms(const ResArgs &a, const Node &mi, double Pi,
-                                           const double qi[5], const double Ai[3], double iJi,
-                                           long long pg, int l, double s, double v[9]) {
+// Data of the partner node of a face node: state, metric row of the face direction and, when the
+// interior penalty needs it, J.
+struct FaceNbr {
+    double q[5];
+    double A[3];
+    double J;
+};
+
+template <bool VISC>
+__device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, int l, FaceNbr &n) {
     const long long nodes = a.nodes;
-    const double gm1 = a.gamma - 1.0, isw = a.isw;
-    double qn[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) qn[c] = a.q[c * nodes + pg];
-    const double An0 = a.metric[(3 * l + 0) * nodes + pg];
-    const double An1 = a.metric[(3 * l + 1) * nodes + pg];
-    const double An2 = a.metric[(3 * l + 2) * nodes + pg];
+    for (int c = 0; c < 5; ++c) n.q[c] = a.q[c * nodes + pg];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) n.A[m] = a.metric[(3 * l + m) * nodes + pg];
+    n.J = (VISC && a.eta != 0.0) ? a.jac[pg] : 1.0;
+}
+
+// Interface terms at one face node i of face (l, s) with partner data nb: the EC shared flux
+// replacing the own flux, the Lax-Friedrichs dissipation and, for viscous problems, the interior
+// penalty (v[0..4]) and the SAT^theta increment of theta_l (v[5..8]).
+// Own-side quantities of a face node that do not depend on the face: primitives, pressure, sound
+// speed, temperature, conservative state and 1/J.
+struct FaceOwn {
+    Node m;
+    double P, c, T, iJ;
+    const double *q;
+};
+
+__device__ __forceinline__ FaceOwn face_own(const ResArgs &a, const Node &m, double P,
+                                            const double q[5], double iJ) {
+    FaceOwn o;
+    o.m = m;
+    o.P = P;
+    o.c = sqrt(a.gamma * P / m.rho);
+    o.T = rcp(2.0 * a.R * m.beta);
+    o.iJ = iJ;
+    o.q = q;
+    return o;
+}
+
+template <int FLUX, bool VISC>
+__device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
+                                           const FaceNbr &nb, double s, double v[9]) {
+    const Node &mi = ow.m;
+    const double Pi = ow.P, *qi = ow.q, iJi = ow.iJ;
+    const double gm1 = a.gamma - 1.0, isw = a.isw;
+    const double *qn = nb.q;
+    const double An0 = nb.A[0], An1 = nb.A[1], An2 = nb.A[2];
     Node o;
     double Pn;
     primitives_nolog(qn, gm1, o, Pn);
@@ -307,7 +341,7 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const Node &mi, dou
     for (int c = 0; c < 5; ++c) v[c] = -s * isw * f[c];
     if (a.iface_diss) {
         const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-        const double li = fabs(mi.u1 * n0 + mi.u2 * n1 + mi.u3 * n2) + sqrt(a.gamma * Pi / mi.rho) * nn;
+        const double li = fabs(mi.u1 * n0 + mi.u2 * n1 + mi.u3 * n2) + ow.c * nn;
         const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
         const double cf = -0.5 * fmax(li, lo) * isw;
 #pragma unroll
@@ -321,17 +355,25 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const Node &mi, dou
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[5 + c] = ct * (wn[c] - wi[c]);
         if (a.eta != 0.0) {
-            const double iJn = rcp(a.jac[pg]);
+            const double iJn = rcp(nb.J);
             double dw[4], pi_[4], pn_[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) dw[c] = wi[c] - wn[c];
-            visc_flux_rank1(Ai[0], Ai[1], Ai[2], iJi, dw, mi.u1, mi.u2, mi.u3, rcp(iTi), a.mu, a.kap, pi_);
+            visc_flux_rank1(Ai[0], Ai[1], Ai[2], iJi, dw, mi.u1, mi.u2, mi.u3, ow.T, a.mu, a.kap, pi_);
             visc_flux_rank1(An0, An1, An2, iJn, dw, o.u1, o.u2, o.u3, rcp(iTn), a.mu, a.kap, pn_);
             const double cf = -0.5 * a.eta * isw;
 #pragma unroll
             for (int c = 0; c < 4; ++c) v[c + 1] = fma(cf, pi_[c] + pn_[c], v[c + 1]);
         }
     }
+}
+
+template <int FLUX, bool VISC>
+__device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
+                                           long long pg, int l, double s, double v[9]) {
+    FaceNbr nb;
+    load_face_nbr<VISC>(a, pg, l, nb);
+    face_terms<FLUX, VISC>(a, ow, Ai, nb, s, v);
 }
 
 }  // namespace

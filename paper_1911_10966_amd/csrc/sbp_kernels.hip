@@ -225,7 +225,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 mi.k = s_buf[F_K * NODES + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, mi, Pi, qi, Ai, iJi, pg, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, l, side ? 1.0 : -1.0, v);
             }
 #pragma unroll
             for (int c = 0; c < NV; ++c) fsl[c * FACE_ITEMS + it] = v[c];
@@ -251,6 +251,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         }
     } else {
         // small elements: most nodes lie on faces, so each node walks its own faces
+        const FaceOwn own = face_own(a, me, Pme, q, iJ);
         if (active) {
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
@@ -265,7 +266,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 faces |= 1 << l;
                 const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
                 double v[9];
-                face_terms<FLUX, VISC>(a, me, Pme, q, A[l], iJ, pg, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, own, A[l], pg, l, side ? 1.0 : -1.0, v);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {

@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + j1 + N * j2);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, mi, Pi, qi, Ai, iJi, pg, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, l, side ? 1.0 : -1.0, v);
             }
         }
 #pragma unroll
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + t + N * il);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, mi, Pi, qi, Ai, iJi, pg, 2, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, 2, side ? 1.0 : -1.0, v);
             }
         }
 #pragma unroll
