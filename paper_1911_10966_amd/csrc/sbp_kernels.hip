@@ -12,18 +12,27 @@
 namespace sbp {
 namespace {
 
-// Doubles of LDS per node in the residual kernel: node data (8), two metric-row areas (6), two
-// mailboxes (10).  For N >= 6 the face slots of the interface work items (6 N^2 x 9 per element)
-// reuse the 16 fields after the node data.
-constexpr int LDS_FIELDS = 24;
+// Doubles of LDS per node in the residual kernel.  Viscous tiles: node data (8), two metric-row
+// areas (6), two mailboxes (10).  Inviscid tiles use fewer registers, so LDS is what limits their
+// occupancy: they keep one metric-row area and recompute |U|^2 of a partner instead of staging it,
+// 20 fields, which lets a CU hold 4 waves per SIMD of N = 5 elements.  For N >= 6 the face slots of
+// the interface work items (6 N^2 x 9 or x 5 per element) reuse the fields from 8 on.
+constexpr int tile_fields(bool visc) { return visc ? 24 : 20; }
+
+// Element size from which the interface terms run as (face, face node) work items.
+constexpr int kFaceItemsFrom = 6;
 
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
 template <int N, int EPW, bool VISC, int FLUX>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
                                               const double *s_D) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
-    constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6, F_K = 7;
-    constexpr int F_A0 = 8, F_A1 = 11, F_MSG0 = 14, F_MSG1 = 19;
+    constexpr bool COMPACT = !VISC;  // see tile_fields
+    constexpr int LDS_FIELDS = tile_fields(VISC);
+    constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6;
+    constexpr int F_K = COMPACT ? -1 : 7;
+    constexpr int F_A0 = COMPACT ? 7 : 8, F_A1 = COMPACT ? 7 : 11;
+    constexpr int F_MSG0 = COMPACT ? 10 : 14, F_MSG1 = COMPACT ? 15 : 19;
 
     const int tid = threadIdx.x;
     const int slot = tid / N3;
@@ -70,7 +79,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         s_buf[F_B * NODES + tid] = me.beta;
         s_buf[F_LR * NODES + tid] = me.lrho;
         s_buf[F_LB * NODES + tid] = me.lbeta;
-        s_buf[F_K * NODES + tid] = me.k;
+        if constexpr (!COMPACT) s_buf[F_K * NODES + tid] = me.k;
     }
 
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -107,6 +116,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int fa = (l & 1) ? F_A1 : F_A0;
+            if constexpr (COMPACT && N % 2 == 0) {
+                // one metric area: the last half-round of the previous direction still reads it
+                if (l > 0) __syncthreads();
+            }
             if (tid < NODES) {
                 s_buf[(fa + 0) * NODES + tid] = A[l][0];
                 s_buf[(fa + 1) * NODES + tid] = A[l][1];
@@ -125,7 +138,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 o.beta = s_buf[F_B * NODES + pn];
                 o.lrho = s_buf[F_LR * NODES + pn];
                 o.lbeta = s_buf[F_LB * NODES + pn];
-                o.k = s_buf[F_K * NODES + pn];
+                if constexpr (COMPACT) o.k = fma(o.u1, o.u1, fma(o.u2, o.u2, o.u3 * o.u3));
+                else o.k = s_buf[F_K * NODES + pn];
                 const double n0 = A[l][0] + s_buf[(fa + 0) * NODES + pn];
                 const double n1 = A[l][1] + s_buf[(fa + 1) * NODES + pn];
                 const double n2 = A[l][2] + s_buf[(fa + 2) * NODES + pn];
@@ -172,13 +186,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     const double iJ = rcp(J);
 
     // ---- interface terms: EC interface flux, Lax-Friedrichs dissipation, SAT^theta, IP --------
+    // The SAT^theta increments stay in LDS until the gradient phase (fields 8.. are free after the
+    // pair loop): in the face slots for N >= 6, in per-node fields 8 + 4 l + c otherwise.
     int faces = 0;
-    double dth[3][4];
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dth[l][c] = 0.0;
-    if constexpr (N >= 6) {
+    if constexpr (N >= kFaceItemsFrom) {
         // (face, face node) work items spread over all lanes: only 6/N of the nodes lie on a face
         // of a given direction, so a per-node loop over directions would leave most lanes idle.
         // Each item leaves its terms in an LDS face slot (over the metric/mailbox areas); each
@@ -222,7 +233,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 mi.beta = s_buf[F_B * NODES + pl];
                 mi.lrho = s_buf[F_LR * NODES + pl];
                 mi.lbeta = s_buf[F_LB * NODES + pl];
-                mi.k = s_buf[F_K * NODES + pl];
+                if constexpr (COMPACT) mi.k = fma(mi.u1, mi.u1, fma(mi.u2, mi.u2, mi.u3 * mi.u3));
+                else mi.k = s_buf[F_K * NODES + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
                 face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, l, side ? 1.0 : -1.0, v);
@@ -243,10 +255,6 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int it = (slot * 6 + 2 * l + side) * N2 + tangential_index<N>(l, i1, i2, i3);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += fsl[c * FACE_ITEMS + it];
-                if constexpr (VISC) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) dth[l][c] = fsl[(5 + c) * FACE_ITEMS + it];
-                }
             }
         }
     } else {
@@ -271,7 +279,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) dth[l][c] = v[5 + c];
+                    for (int c = 0; c < 4; ++c) s_buf[(8 + 4 * l + c) * NODES + tid] = v[5 + c];
                 }
             }
         }
@@ -291,7 +299,19 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) th[d][c] = dth[d][c];
+            for (int c = 0; c < 4; ++c) th[d][c] = 0.0;
+            if (faces & (1 << d)) {
+                if constexpr (N >= kFaceItemsFrom) {
+                    constexpr int FACE_ITEMS = EPW * 6 * N2;
+                    const int side = idx[d] == N - 1 ? 1 : 0;
+                    const int it = (slot * 6 + 2 * d + side) * N2 + tangential_index<N>(d, i1, i2, i3);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) th[d][c] = s_buf[8 * NODES + (5 + c) * FACE_ITEMS + it];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) th[d][c] = s_buf[(8 + 4 * d + c) * NODES + tid];
+                }
+            }
             if (tid < NODES) {
                 const int il = idx[d];
 #pragma unroll
@@ -373,7 +393,7 @@ __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
 __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
 k_residual(const GroupArgs g) {
     constexpr int N2 = N * N, NODES = EPW * N * N * N;
-    __shared__ double s_buf[LDS_FIELDS * NODES];
+    __shared__ double s_buf[tile_fields(VISC) * NODES];
     __shared__ double s_D[N2];
     if (threadIdx.x < N2) s_D[threadIdx.x] = g.D[threadIdx.x];
     if constexpr (!PERSIST) {
