@@ -68,11 +68,10 @@ def algorithmic_bytes(p, K, viscous):
 # HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
 # this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
 # copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
-TRAFFIC = {"sha256": "ef28b44f0de467253ee8f39dd8c4abd5cbb51009e86332e867f9631a068aed5f",
+TRAFFIC = {"sha256": "83b2e02238610425e757cbc154416b6ec68bbabc5e0f0b843fc93b1cd5cfd7b8",
            "workload": "ns_tgv_p4_e32",
            # bytes per launch by residual schedule index (degree 4)
-           "bytes": {0: 1142004872, 1: 1180406190, 2: 1043473975, 3: 1031049168, 4: 1141587051,
-                     5: 1170930312, 6: 1816568060}}
+           "bytes": {0: 1360113144, 1: 1343264656, 2: 1049337040, 3: 1034077840, 4: 1358553544, 5: 1344933783, 6: 1296623497}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 
@@ -372,7 +371,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ns_tgv_p4_e32")
-    ap.add_argument("--cpu-sample", type=int, default=12288, help="elements in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=32768, help="elements in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--kernel-reps", type=int, default=10)
