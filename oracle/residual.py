@@ -19,7 +19,12 @@ are garbled or that defer to other papers:
       sum_l D_l fhat_l + (s/(2 w_end)) (fhat_l,nu - fhat_l,i)
       - (eta / w_end) (Chat_ll,i + Chat_ll,nu)/2 (w_i - w_nu),
   Chat_ll = sum_{m,j} A_lm C_mj A_lj / J (eq. Chatij with the summation index fixed);
-* the output is dq/dt: the sum of the terms divided by J.
+* the output is dq/dt: the sum of the terms divided by J, plus an optional source term (the
+  forcing of a manufactured solution, given per node);
+* a boundary face (neighbour index -1) is an interface with a ghost element whose face node
+  carries the prescribed (Dirichlet) state and the own node's metrics and J: the inviscid SAT,
+  dissipation, SAT^theta and interior penalty keep their interface form with the ghost data,
+  and SAT^V vanishes there (the boundary viscous flux is the interior one).
 """
 from __future__ import annotations
 
@@ -92,8 +97,22 @@ def volume_term(q, metric, sbp, prm: Params):
     return V
 
 
-def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params):
-    """Interface SAT and local Lax-Friedrichs dissipation for the elements ``elems``."""
+def _partner(arr_all, nbr, elems, f, own, nb, l, bc_arr):
+    """Face-node values of the partner across face f for the elements ``elems``: the neighbour's
+    mirrored face node, or, on boundary faces (neighbour -1), ``bc_arr`` at the own face node."""
+    nb_e = nbr[elems, f]
+    bnd = nb_e < 0
+    out = _take(arr_all[..., np.where(bnd, elems, nb_e), :, :, :], nb, l)
+    if bnd.any():
+        if bc_arr is None:
+            raise ValueError("boundary face without boundary data")
+        out[..., bnd, :, :] = _take(bc_arr[..., elems[bnd], :, :, :], own, l)
+    return out
+
+
+def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
+    """Interface SAT and local Lax-Friedrichs dissipation for the elements ``elems``; ``bc`` is
+    the Dirichlet state used on boundary faces."""
     flux = G.TWO_POINT[prm.two_point]
     gas = prm.gas
     q = q_all[:, elems]
@@ -101,9 +120,9 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params):
     w_end = sbp.w[0]
     for l, s, f, own, nb in _faces(sbp.p):
         qi = _take(q, own, l)
-        qn = _take(q_all[:, nbr[elems, f]], nb, l)
+        qn = _partner(q_all, nbr, elems, f, own, nb, l, bc)
         Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
-        An = _take(metric_all[3 * l:3 * l + 3, nbr[elems, f]], nb, l)
+        An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
         nbar = 0.5 * (Ai + An)
         sat = -(s / w_end) * (G.contract(flux(qi, qn, gas), nbar) - G.contract(G.euler_flux(qi, gas), Ai))
         if prm.iface_diss:
@@ -122,7 +141,7 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params):
     return out
 
 
-def gradient_theta(q_all, nbr, elems, sbp, prm: Params):
+def gradient_theta(q_all, nbr, elems, sbp, prm: Params, bc=None):
     """theta_a = D_a w + SAT^theta for the elements ``elems``, shape (3, 5, n, N, N, N)."""
     gas = prm.gas
     w = G.entropy_variables(q_all[:, elems], gas)
@@ -130,15 +149,15 @@ def gradient_theta(q_all, nbr, elems, sbp, prm: Params):
     w_end = sbp.w[0]
     for a, s, f, own, nb in _faces(sbp.p):
         wi = _take(w, own, a)
-        wn = _take(G.entropy_variables(q_all[:, nbr[elems, f]], gas), nb, a)
+        wn = G.entropy_variables(_partner(q_all, nbr, elems, f, own, nb, a, bc), gas)
         th[a][_index(w.ndim, own, a)] += (s / (2.0 * w_end)) * (wn - wi)
     return th
 
 
-def contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params):
+def contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None):
     """fhat_l = sum_m A_lm F^V_m with F^V_m = sum_j C_mj g_j and g_j = sum_a A_aj theta_a / J;
     shape (3, 5, n, N, N, N)."""
-    th = gradient_theta(q_all, nbr, elems, sbp, prm)
+    th = gradient_theta(q_all, nbr, elems, sbp, prm, bc)
     A = metric_all[:, elems]
     J = jac_all[elems]
     g = np.stack([sum(A[3 * a + j] * th[a] for a in range(3)) / J for j in range(3)])
@@ -152,13 +171,14 @@ def chat_ll(q, A_l, J, gas):
     return sum(A_l[m] * C[m, j] * A_l[j] for m in range(3) for j in range(3)) / J
 
 
-def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params):
+def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None):
     """sum_l D_l fhat_l + SAT^V + IP for the elements ``elems`` (eq. NSL, eq. MacroForm)."""
     gas = prm.gas
     elems = np.asarray(elems)
     ring = np.unique(np.concatenate([elems, nbr[elems].ravel()]))
+    ring = ring[ring >= 0]
     pos = {int(e): i for i, e in enumerate(ring)}
-    fh_ring = contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, ring, sbp, prm)
+    fh_ring = contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, ring, sbp, prm, bc)
     own_pos = np.array([pos[int(e)] for e in elems])
     fh = fh_ring[:, :, own_pos]
     out = sum(apply_D(sbp.D, fh[l], l) for l in range(3))
@@ -167,26 +187,32 @@ def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params):
     w = G.entropy_variables(q, gas)
     for l, s, f, own, nb in _faces(sbp.p):
         nb_e = nbr[elems, f]
-        nb_pos = np.array([pos[int(e)] for e in nb_e])
+        bnd = nb_e < 0
+        nb_pos = np.array([pos[int(e)] if e >= 0 else own_pos[i] for i, e in enumerate(nb_e)])
         fi = _take(fh[l], own, l)
         fn = _take(fh_ring[l][:, nb_pos], nb, l)
         sat_v = (s / (2.0 * w_end)) * (fn - fi)
+        sat_v[:, bnd] = 0.0   # no SAT^V on boundary faces
         # interior penalty
-        qi, qn = _take(q, own, l), _take(q_all[:, nb_e], nb, l)
+        qi, qn = _take(q, own, l), _partner(q_all, nbr, elems, f, own, nb, l, bc)
         wi, wn = _take(w, own, l), G.entropy_variables(qn, gas)
         Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
-        An = _take(metric_all[3 * l:3 * l + 3, nb_e], nb, l)
-        Ji, Jn = _take(jac_all[elems], own, l), _take(jac_all[nb_e], nb, l)
+        An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
+        Ji = _take(jac_all[elems], own, l)
+        Jn = _partner(jac_all, nbr, elems, f, own, nb, l, jac_all)
         Lm = 0.5 * (chat_ll(qi, Ai, Ji, gas) + chat_ll(qn, An, Jn, gas))
         ip = -(prm.eta / w_end) * np.einsum("ab...,b...->a...", Lm, wi - wn)
         out[_index(out.ndim, own, l)] += sat_v + ip
     return out
 
 
-def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chunk=None):
+def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chunk=None, bc=None,
+             source=None):
     """dq/dt for the elements ``elems`` (all by default), shape (5, n, N, N, N).
 
     ``chunk`` splits the element list into groups evaluated one after another (memory only).
+    ``bc`` (shape of q) holds the Dirichlet state read at the face nodes of boundary faces
+    (neighbour index -1); ``source`` (shape of q) is added to dq/dt.
     """
     K = q_all.shape[1]
     if elems is None:
@@ -194,14 +220,17 @@ def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chun
     elems = np.asarray(elems)
     if chunk is not None and len(elems) > chunk:
         return np.concatenate([residual(q_all, metric_all, jac_all, nbr, sbp, prm,
-                                        elems[i:i + chunk]) for i in range(0, len(elems), chunk)],
-                              axis=1)
+                                        elems[i:i + chunk], bc=bc, source=source)
+                               for i in range(0, len(elems), chunk)], axis=1)
     q = q_all[:, elems]
     rhs = -volume_term(q, metric_all[:, elems], sbp, prm)
-    rhs = rhs + inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm)
+    rhs = rhs + inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm, bc)
     if prm.gas.mu != 0.0:
-        rhs = rhs + viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm)
-    return rhs / jac_all[elems]
+        rhs = rhs + viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm, bc)
+    out = rhs / jac_all[elems]
+    if source is not None:
+        out = out + source[:, elems]
+    return out
 
 
 def rk4_step(f, q, dt):

@@ -27,7 +27,7 @@ F64 = torch.float64
 
 @dataclasses.dataclass
 class Problem:
-    """One periodic compressible Navier-Stokes problem on a warped box."""
+    """One compressible Navier-Stokes problem on a warped box (periodic unless stated)."""
 
     name: str
     p: int
@@ -41,7 +41,8 @@ class Problem:
     eta: float = 1.0             # interior-penalty coefficient
     iface_diss: int = 1          # 1 -> local Lax-Friedrichs interface dissipation
     two_point: int = 0           # 0 -> Chandrashekar flux, 1 -> central (test only)
-    init: str = "random"         # random | tgv | constant | vortex | shear
+    init: str = "random"         # random | tgv | constant | vortex | shear | mms
+    periodic: bool = True        # False: the six box faces are Dirichlet boundaries
     seed: int = 0
     Ma: float = 0.3
     u_rms: Optional[float] = None  # per-component rms velocity of the random state
@@ -82,6 +83,17 @@ def _random_ns(name, p, E, A, Ma, Re, seed, L=2.0):
                    seed=seed, Ma=Ma, u_rms=u_rms_mag / math.sqrt(3.0), Re=Re)
 
 
+def mms_problem(p: int, E: int, A: float = 0.0, two_point: int = 0, iface_diss: int = 1,
+                mu: Optional[float] = None) -> Problem:
+    """The manufactured-solution problem of the viscous error-vs-cost study on the unit cube,
+    Dirichlet boundaries on all faces (see ``workloads.mms``)."""
+    from . import mms
+    return Problem(name=f"mms_p{p}_e{E}", p=p, E=E, L=1.0, A=A, gamma=mms.GAMMA, R=mms.R_GAS,
+                   mu=mms.MU if mu is None else mu, Pr=mms.PR, init="mms", periodic=False,
+                   two_point=two_point, iface_diss=iface_diss, Ma=800.0 / math.sqrt(1.4e5),
+                   Re=mms.RE)
+
+
 def config(name: str) -> Problem:
     """The single-problem workloads by name (the batch is ``batch_config``)."""
     if name == "euler_p3_e4":
@@ -120,13 +132,18 @@ def batch_config(n_prob: int = 256, seed_base: int = 4000, p_range=(2, 8), e_ran
 # ----------------------------------------------------------------------------------
 # Mesh
 # ----------------------------------------------------------------------------------
-def neighbours(E: int) -> np.ndarray:
-    """[K, 6] int32 face-neighbour table of the periodic E^3 grid."""
+def neighbours(E: int, periodic: bool = True) -> np.ndarray:
+    """[K, 6] int32 face-neighbour table of the E^3 grid: periodic wrap-around, or -1 on the faces
+    that lie on the box boundary."""
     e = np.arange(E ** 3)
     e1, e2, e3 = e % E, (e // E) % E, e // (E * E)
 
     def idx(a, b, c):
-        return (a % E) + E * (b % E) + E * E * (c % E)
+        n = (a % E) + E * (b % E) + E * E * (c % E)
+        if not periodic:
+            out = (a < 0) | (a >= E) | (b < 0) | (b >= E) | (c < 0) | (c >= E)
+            n = np.where(out, -1, n)
+        return n
 
     nb = np.stack([idx(e1 - 1, e2, e3), idx(e1 + 1, e2, e3),
                    idx(e1, e2 - 1, e3), idx(e1, e2 + 1, e3),
@@ -230,6 +247,11 @@ def primitive_state(prob: Problem, x: torch.Tensor):
         T = torch.ones_like(x1)
         p = rho * prob.R * T
         return rho, u, p
+    if prob.init == "mms":
+        from . import mms
+        rho, u, p = mms.primitives(x)
+        return (torch.as_tensor(rho, dtype=F64, device=x.device), torch.as_tensor(u, dtype=F64, device=x.device),
+                torch.as_tensor(p, dtype=F64, device=x.device))
     if prob.init == "constant":
         r, a, b, c, pp = prob.const
         one = torch.ones_like(x[0])
