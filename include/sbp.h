@@ -70,6 +70,16 @@ typedef struct sbp_problem {
     double eta;             /* interior-penalty coefficient >= 0                               */
     int32_t two_point;      /* SBP_FLUX_*: inviscid volume form and interface flux            */
     int32_t reserved;       /* must be 0                                                       */
+    /* Optional device SoA [5][K*N^3] arrays (NULL = absent):
+     * bc_state: prescribed (Dirichlet) state.  A face with nbr == -1 is then a boundary face: its
+     *   partner is a ghost node carrying bc_state at the own face node, with the own node's metrics
+     *   and J; the inviscid SAT, dissipation, SAT^theta and interior penalty keep their interface
+     *   form with that partner, and SAT^V vanishes (the boundary viscous flux is the interior one).
+     *   Only the entries at face nodes of boundary faces are read.  Without bc_state, nbr == -1 is
+     *   a mesh error like any other index outside [0, K).
+     * source: forcing added to dq/dt (e.g. of a manufactured solution). */
+    const double *bc_state;
+    const double *source;
 } sbp_problem;
 
 /* Library version, for diagnostics. */
@@ -114,8 +124,9 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
 /* Vector-Jacobian product qbar = (d(dq/dt)/dq)^T gbar of the residual of sbp_residual, with each
  * element recomputing its forward intermediates (no two-point fluxes are stored) and interface
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
- * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0); other fluxes give
- * SBP_ERR_ARG, degrees above SBP_MAX_VJP_P give SBP_ERR_DEGREE.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
+ * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0) on periodic problems
+ * (bc_state == NULL); other fluxes or boundary data give SBP_ERR_ARG, degrees above SBP_MAX_VJP_P
+ * give SBP_ERR_DEGREE.  A source term does not enter the product.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
  * in the interface dissipation takes the own side on ties. */
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
                      double *qbar, void *ws, size_t ws_bytes, void *stream);

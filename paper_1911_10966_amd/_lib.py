@@ -37,6 +37,8 @@ class sbp_problem(ctypes.Structure):
         ("eta", ctypes.c_double),
         ("two_point", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("bc_state", ctypes.c_void_p),
+        ("source", ctypes.c_void_p),
     ]
 
 

@@ -62,7 +62,8 @@ def metrics(p: int, coords: torch.Tensor):
 
 @dataclass
 class Problem:
-    """One periodic problem on the device: degree, element count, neighbour table, metrics, constants."""
+    """One problem on the device: degree, element count, neighbour table, metrics, constants, and
+    optionally Dirichlet boundary data and a source term."""
 
     p: int
     n_elem: int
@@ -76,6 +77,8 @@ class Problem:
     eta: float = 1.0
     iface_diss: int = 1
     two_point: int = 0
+    bc_state: Optional[torch.Tensor] = None   # float64 (5, nodes): Dirichlet state, faces with nbr -1
+    source: Optional[torch.Tensor] = None     # float64 (5, nodes): added to dq/dt
 
     @property
     def nodes(self) -> int:
@@ -85,9 +88,17 @@ class Problem:
         _need(self.nbr, torch.int32, "nbr")
         _need(self.metric, F64, "metric")
         _need(self.jac, F64, "jac")
+        extra = []
+        for name in ("bc_state", "source"):
+            t = getattr(self, name)
+            if t is not None:
+                _need(t, F64, name)
+                if t.numel() != 5 * self.nodes:
+                    raise ValueError(f"{name} has {t.numel()} entries, expected {5 * self.nodes}")
+            extra.append(None if t is None else t.data_ptr())
         return _lib.sbp_problem(self.p, self.iface_diss, self.n_elem, self.nbr.data_ptr(),
                                 self.metric.data_ptr(), self.jac.data_ptr(), self.gamma, self.R,
-                                self.mu, self.Pr, self.eta, self.two_point, 0)
+                                self.mu, self.Pr, self.eta, self.two_point, 0, *extra)
 
 
 class ProblemSet:

@@ -137,6 +137,7 @@ int check_problem(const sbp_problem &pr) {
     if (!(pr.gamma > 1.0) || !(pr.R > 0.0) || !(pr.mu >= 0.0) || !(pr.eta >= 0.0)) return SBP_ERR_ARG;
     if (pr.mu > 0.0 && !(pr.Pr > 0.0)) return SBP_ERR_ARG;
     if (pr.two_point < 0 || pr.two_point > 3 || pr.reserved != 0) return SBP_ERR_ARG;
+    if ((pr.bc_state && !aligned8(pr.bc_state)) || (pr.source && !aligned8(pr.source))) return SBP_ERR_ARG;
     if (pr.iface_diss != 0 && pr.iface_diss != 1) return SBP_ERR_ARG;
     return SBP_OK;
 }
@@ -275,6 +276,8 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
             d.nbr = pr.nbr;
             d.trace = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.trace[b]) : nullptr;
             d.thb = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.thb[b]) : nullptr;
+            d.bc = pr.bc_state;
+            d.src = pr.source;
             d.K = pr.n_elem;
             d.nodes = nodes_of(pr);
             d.off = off[b];
@@ -422,7 +425,7 @@ int record_rk_graph(Plan *plan, double *q, const double *dt, char *ws, const Lay
 
 extern "C" {
 
-int sbp_version(void) { return 100; }
+int sbp_version(void) { return 110; }
 
 const char *sbp_error_string(int code) {
     switch (code) {
@@ -517,7 +520,8 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
         return SBP_ERR_ARG;
     for (int b = 0; b < n_prob; ++b) {
-        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR) return SBP_ERR_ARG;
+        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].bc_state != nullptr)
+            return SBP_ERR_ARG;
         if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
     }
     char *w = static_cast<char *>(ws);

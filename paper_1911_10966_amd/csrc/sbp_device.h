@@ -258,6 +258,8 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
     a.nbr = P.nbr;
     a.trace = P.trace;
     a.aux = P.thb;
+    a.bc = P.bc;
+    a.src = P.src;
     a.status = g.status;
     a.D = g.D;
     a.K = P.K;
@@ -283,11 +285,22 @@ struct FaceNbr {
     double J;
 };
 
+// Kind of the face across which an element sees neighbour index nb: 1 interior (a valid
+// neighbour), 2 boundary (nb == -1 with boundary data present), 0 invalid (a mesh error).
+__device__ __forceinline__ int face_kind(const ResArgs &a, long long nb) {
+    if (nb >= 0 && nb < a.K) return 1;
+    return (nb == -1 && a.bc != nullptr) ? 2 : 0;
+}
+
+// Partner of a face node: node pg of the neighbour, or on a boundary face (bnd) a ghost at the
+// own node pg carrying the prescribed state with the own metrics and J.
 template <bool VISC>
-__device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, int l, FaceNbr &n) {
+__device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, bool bnd, int l,
+                                              FaceNbr &n) {
     const long long nodes = a.nodes;
+    const double *qs = bnd ? a.bc : a.q;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) n.q[c] = a.q[c * nodes + pg];
+    for (int c = 0; c < 5; ++c) n.q[c] = qs[c * nodes + pg];
 #pragma unroll
     for (int m = 0; m < 3; ++m) n.A[m] = a.metric[(3 * l + m) * nodes + pg];
     n.J = (VISC && a.eta != 0.0) ? a.jac[pg] : 1.0;
@@ -370,9 +383,9 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
 
 template <int FLUX, bool VISC>
 __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
-                                           long long pg, int l, double s, double v[9]) {
+                                           long long pg, bool bnd, int l, double s, double v[9]) {
     FaceNbr nb;
-    load_face_nbr<VISC>(a, pg, l, nb);
+    load_face_nbr<VISC>(a, pg, bnd, l, nb);
     face_terms<FLUX, VISC>(a, ow, Ai, nb, s, v);
 }
 

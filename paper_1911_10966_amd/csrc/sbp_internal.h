@@ -18,6 +18,8 @@ struct ResArgs {
     const int32_t *nbr;    // [K][6]
     double *trace;         // viscous face traces [K][6][4][N^2] (mu > 0 only)
     double *aux;           // viscous per-node scratch of the plane kernels, [16][nodes] (mu > 0 only)
+    const double *bc;      // Dirichlet state of boundary faces (nbr == -1), SoA [5][nodes], or null
+    const double *src;     // source added to dq/dt, SoA [5][nodes], or null
     int *status;           // sticky flags
     const double *D;       // [N*N] collocation derivative
     long long K;
@@ -38,6 +40,8 @@ struct ProbDev {
     const int32_t *nbr;
     double *trace;
     double *thb;
+    const double *bc;
+    const double *src;
     long long K;
     long long nodes;
     long long off;

@@ -188,7 +188,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     // ---- interface terms: EC interface flux, Lax-Friedrichs dissipation, SAT^theta, IP --------
     // The SAT^theta increments stay in LDS until the gradient phase (fields 8.. are free after the
     // pair loop): in the face slots for N >= 6, in per-node fields 8 + 4 l + c otherwise.
-    int faces = 0;
+    // `faces` marks the node's interior faces (SAT^V), `sfaces` interior and boundary faces.
+    int faces = 0, sfaces = 0;
     if constexpr (N >= kFaceItemsFrom) {
         // (face, face node) work items spread over all lanes: only 6/N of the nodes lie on a face
         // of a given direction, so a per-node loop over directions would leave most lanes idle.
@@ -209,9 +210,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             double v[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) v[c] = 0.0;
-            const long long nb = ee < a.K ? (long long)a.nbr[ee * 6 + f] : -1;
-            if (ee < a.K && (nb < 0 || nb >= a.K)) atomicOr(a.status, FLAG_MESH);
-            if (ee < a.K && nb >= 0 && nb < a.K) {
+            const long long nb = ee < a.K ? (long long)a.nbr[ee * 6 + f] : 0;
+            const int kind = ee < a.K ? face_kind(a, nb) : 0;
+            if (ee < a.K && kind == 0) atomicOr(a.status, FLAG_MESH);
+            if (kind != 0) {
                 const int il = side ? N - 1 : 0;
                 const int ta = t % N, tb = t / N;
                 const int lno = l == 0 ? il + N * ta + N2 * tb
@@ -219,7 +221,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int sl = l == 0 ? 1 : (l == 1 ? N : N2);
                 const int pl = es * N3 + lno;
                 const long long go = ee * N3 + lno;
-                const long long pg = nb * N3 + lno + (N - 1 - 2 * il) * sl;
+                const long long pg = kind == 1 ? nb * N3 + lno + (N - 1 - 2 * il) * sl : go;
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -237,7 +239,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 else mi.k = s_buf[F_K * NODES + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
+                                       side ? 1.0 : -1.0, v);
             }
 #pragma unroll
             for (int c = 0; c < NV; ++c) fsl[c * FACE_ITEMS + it] = v[c];
@@ -249,9 +252,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int il = idx[l];
                 if (il != 0 && il != N - 1) continue;
                 const int side = (il == N - 1) ? 1 : 0;
-                const long long nb = a.nbr[e * 6 + 2 * l + side];
-                if (nb < 0 || nb >= a.K) continue;
-                faces |= 1 << l;
+                const int kind = face_kind(a, a.nbr[e * 6 + 2 * l + side]);
+                if (kind == 0) continue;
+                if (kind == 1) faces |= 1 << l;
+                sfaces |= 1 << l;
                 const int it = (slot * 6 + 2 * l + side) * N2 + tangential_index<N>(l, i1, i2, i3);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += fsl[c * FACE_ITEMS + it];
@@ -267,14 +271,16 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 if (il != 0 && il != N - 1) continue;
                 const int side = (il == N - 1) ? 1 : 0;
                 const long long nb = a.nbr[e * 6 + 2 * l + side];
-                if (nb < 0 || nb >= a.K) {
+                const int kind = face_kind(a, nb);
+                if (kind == 0) {
                     atomicOr(a.status, FLAG_MESH);
                     continue;
                 }
-                faces |= 1 << l;
-                const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
+                if (kind == 1) faces |= 1 << l;
+                sfaces |= 1 << l;
+                const long long pg = kind == 1 ? nb * N3 + ln + (N - 1 - 2 * il) * stride[l] : g;
                 double v[9];
-                face_terms<FLUX, VISC>(a, own, A[l], pg, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, own, A[l], pg, kind == 2, l, side ? 1.0 : -1.0, v);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {
@@ -300,7 +306,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         for (int d = 0; d < 3; ++d) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) th[d][c] = 0.0;
-            if (faces & (1 << d)) {
+            if (sfaces & (1 << d)) {
                 if constexpr (N >= kFaceItemsFrom) {
                     constexpr int FACE_ITEMS = EPW * 6 * N2;
                     const int side = idx[d] == N - 1 ? 1 : 0;
@@ -380,8 +386,13 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     }
 
     if (active) {
+        if (a.src) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) a.out[c * nodes + g] = acc[c] * iJ;
+            for (int c = 0; c < 5; ++c) a.out[c * nodes + g] = fma(acc[c], iJ, a.src[c * nodes + g]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) a.out[c * nodes + g] = acc[c] * iJ;
+        }
     }
 }
 

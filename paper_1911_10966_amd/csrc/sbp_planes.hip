@@ -220,14 +220,15 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
             const long long e = ipl / N;
             const int j3 = (int)(ipl - e * N);
             const long long nb = a.nbr[e * 6 + f];
-            if (nb < 0 || nb >= a.K) {
+            const int kind = face_kind(a, nb);
+            if (kind == 0) {
                 atomicOr(a.status, FLAG_MESH);
             } else {
                 const int il = side ? N - 1 : 0;
                 const int j1 = l == 0 ? il : t, j2 = l == 0 ? t : il;
                 const int lno = j1 + N * j2 + N2 * j3;
                 const long long go = e * N3 + lno;
-                const long long pg = nb * N3 + lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N);
+                const long long pg = kind == 1 ? nb * N3 + lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N) : go;
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -236,7 +237,8 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + j1 + N * j2);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
+                                       side ? 1.0 : -1.0, v);
             }
         }
 #pragma unroll
@@ -352,13 +354,14 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
             const long long ee = ipl / N;
             const int j2 = (int)(ipl - ee * N);
             const long long nb = a.nbr[ee * 6 + 4 + side];
-            if (nb < 0 || nb >= a.K) {
+            const int kind = face_kind(a, nb);
+            if (kind == 0) {
                 atomicOr(a.status, FLAG_MESH);
             } else {
                 const int il = side ? N - 1 : 0;
                 const int lno = t + N * j2 + N2 * il;
                 const long long go = ee * N3 + lno;
-                const long long pg = nb * N3 + lno + (N - 1 - 2 * il) * N2;
+                const long long pg = kind == 1 ? nb * N3 + lno + (N - 1 - 2 * il) * N2 : go;
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -367,7 +370,8 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + t + N * il);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, 2, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, 2,
+                                       side ? 1.0 : -1.0, v);
             }
         }
 #pragma unroll
@@ -466,7 +470,8 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
     } else {
         if (on) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) a.out[c * nodes + gn] = acc[c] * iJ;
+            for (int c = 0; c < 5; ++c)
+                a.out[c * nodes + gn] = a.src ? fma(acc[c], iJ, a.src[c * nodes + gn]) : acc[c] * iJ;
         }
     }
 }
@@ -538,9 +543,12 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_c(const GroupArgs 
         }
     }
     const double iJ = rcp(a.jac[gn]);
-    a.out[gn] *= iJ;
+    double r[5];
+    r[0] = a.out[gn] * iJ;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a.out[(c + 1) * nodes + gn] = (a.out[(c + 1) * nodes + gn] + acc[c]) * iJ;
+    for (int c = 0; c < 4; ++c) r[c + 1] = (a.out[(c + 1) * nodes + gn] + acc[c]) * iJ;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a.out[c * nodes + gn] = a.src ? r[c] + a.src[c * nodes + gn] : r[c];
 }
 
 // Curl-form metrics for elements too large for one thread per node: a workgroup holds the

@@ -84,7 +84,8 @@ def primitives(x):
     """(rho, U (3,...), P) of the manufactured solution at coordinates x (3, ...)."""
     f_prim, _ = _symbolic(MU, GAMMA, PR, R_GAS)
     xn = _as_np(x)
-    vals = [np.broadcast_to(np.asarray(v, dtype=np.float64), xn.shape[1:]) for v in f_prim(xn[0], xn[1], xn[2])]
+    vals = [np.array(np.broadcast_to(np.asarray(v, dtype=np.float64), xn.shape[1:]))
+            for v in f_prim(xn[0], xn[1], xn[2])]
     return vals[0], np.stack(vals[1:4]), vals[4]
 
 
