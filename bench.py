@@ -364,6 +364,74 @@ def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=200
     return out
 
 
+def mms_error_vs_cost(P, W, dev, degrees, meshes_of, t_end, cfl, budget_s):
+    """The paper's viscous error-vs-cost study (manufactured supersonic solution on the unit cube,
+    Dirichlet data on every face, Re = 4e6, Ma = 2.14): for ES-C and DC and each degree and mesh,
+    classical RK4 from the exact nodal state to t_end (several passages of the slowest wave through
+    the cube), then the L2 error of the density against the exact solution, the GPU time of the
+    time stepping and the remaining residual (how steady the end state is)."""
+    import math
+    import torch
+    from workloads import mms
+    out = {"t_end": t_end, "cfl": cfl, "Re": mms.RE, "Ma": round(800.0 / math.sqrt(1.4e5), 3),
+           "integrator": "classical RK4, fixed dt", "results": []}
+    smax = mms.speed_max()
+    t_start = time.time()
+    for p in degrees:
+        for E in meshes_of(p):
+            for name, tp in (("ES-C", 0), ("DC", 3)):
+                if time.time() - t_start > budget_s:
+                    out["results"].append({"p": p, "E": E, "scheme": name, "result": "not run (time budget)"})
+                    continue
+                prob = W.mms_problem(p, E, two_point=tp)
+                x1d, w1d, _ = P.lgl_operator(p)
+                x = W.coords(prob, x1d, device=dev)
+                metric, jac = P.metrics(p, x.reshape(3, -1).contiguous())
+                qex = torch.as_tensor(mms.conservative(x), device=dev).reshape(-1).contiguous()
+                src = torch.as_tensor(mms.source(x), device=dev).reshape(-1).contiguous()
+                dp = P.Problem(p=p, n_elem=prob.K,
+                               nbr=torch.as_tensor(W.neighbours(E, periodic=False), device=dev),
+                               metric=metric, jac=jac, gamma=prob.gamma, R=prob.R, mu=prob.mu,
+                               Pr=prob.Pr, eta=prob.eta, iface_diss=1, two_point=tp,
+                               bc_state=qex, source=src)
+                ps = P.ProblemSet([dp])
+                dt0 = cfl * (1.0 / E) / ((p + 1) ** 2 * smax)
+                n = int(math.ceil(t_end / dt0))
+                dt = torch.tensor([t_end / n], dtype=torch.float64, device=dev)
+                q = qex.clone()
+                ps.rk_step(q, dt, 1)
+                torch.cuda.synchronize()
+                q = qex.clone()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ps.rk_step(q, dt, n)
+                e1.record()
+                torch.cuda.synchronize()
+                secs = e0.elapsed_time(e1) / 1e3
+                failed = False
+                try:
+                    ps.status()
+                except P.SBPError:
+                    failed = True
+                w = torch.as_tensor(w1d, dtype=torch.float64, device=dev)
+                w3 = (w[:, None, None] * w[None, :, None] * w[None, None, :]).reshape(-1)
+                wJ = (w3[None, :] * jac.reshape(prob.K, -1)).reshape(-1)
+                q5, x5 = q.reshape(5, -1), qex.reshape(5, -1)
+                err = float(torch.sqrt((wJ * (q5[0] - x5[0]) ** 2).sum() / wJ.sum()))
+                r = ps.residual(q).reshape(5, -1)
+                res = float(torch.sqrt((wJ * (r * r).sum(0)).sum() / (wJ * (src.reshape(5, -1) ** 2).sum(0)).sum()))
+                out["results"].append({"p": p, "E": E, "scheme": name, "dofs": prob.n_nodes,
+                                       "steps": n, "gpu_s": round(secs, 3),
+                                       "result": "failure" if failed or not math.isfinite(err) else "ok",
+                                       "l2_error_rho": err, "residual_rel": res})
+                print(f"mms p={p} E={E} {name}: dofs {prob.n_nodes}, {n} steps, {secs:.2f} s, "
+                      f"L2(rho) {err:.3e}, residual {res:.1e}", file=sys.stderr, flush=True)
+                del ps, dp, q, qex, src, metric, jac
+                torch.cuda.empty_cache()
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -384,6 +452,11 @@ def main():
     ap.add_argument("--robust-t-final", type=float, default=20.0)
     ap.add_argument("--robust-cfl", type=float, default=0.5)
     ap.add_argument("--robust-budget", type=float, default=900.0, help="seconds before skipping runs")
+    ap.add_argument("--mms", action="store_true",
+                    help="run only the manufactured-solution error-vs-cost study (ES-C / DC)")
+    ap.add_argument("--mms-degrees", default="1,3,5,7")
+    ap.add_argument("--mms-t-end", type=float, default=0.02)
+    ap.add_argument("--mms-budget", type=float, default=600.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the plain/batched/VJP secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -408,6 +481,13 @@ def main():
     torch.cuda.set_device(0)
     if args.cost_experiment:
         print(json.dumps({"cost_of_entropy_stability": cost_experiment(P, W, dev, 5)}), flush=True)
+        return 0
+    if args.mms:
+        meshes = {1: (4, 8, 16, 32, 64), 2: (2, 4, 8, 16, 32), 3: (2, 4, 8, 16), 4: (2, 4, 8, 16),
+                  5: (2, 4, 8), 6: (2, 4, 8), 7: (2, 4, 8)}
+        res = mms_error_vs_cost(P, W, dev, [int(v) for v in args.mms_degrees.split(",")],
+                                lambda p: meshes.get(p, (2, 4)), args.mms_t_end, 0.5, args.mms_budget)
+        print(json.dumps({"mms_error_vs_cost": res}), flush=True)
         return 0
     if args.robustness:
         def int_list(spec):

@@ -20,7 +20,6 @@ residual (every term is written in rho, U, P) and is set to 287; Pr = 0.72.
 from __future__ import annotations
 
 import functools
-import math
 
 import numpy as np
 import sympy as sp
