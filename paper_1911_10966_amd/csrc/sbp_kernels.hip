@@ -201,7 +201,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         constexpr int NV = VISC ? 9 : 5;
         static_assert(NV * 6 <= (LDS_FIELDS - 8) * N, "face slots exceed the LDS tile");
         double *fsl = s_buf + 8 * NODES;  // [NV][FACE_ITEMS]
-        for (int it = tid; it < FACE_ITEMS; it += NT) {
+        // at most two items per thread, as straight-line code (a loop here keeps both items' values
+        // live and costs a third of the register file)
+        static_assert(FACE_ITEMS <= 2 * NT, "at most two face items per thread");
+        auto face_item = [&](const int it) {
             const int es = it / (6 * N2);
             const int rem = it - es * 6 * N2;
             const int f = rem / N2, t = rem - f * N2;
@@ -244,6 +247,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             }
 #pragma unroll
             for (int c = 0; c < NV; ++c) fsl[c * FACE_ITEMS + it] = v[c];
+        };
+        if (tid < FACE_ITEMS) face_item(tid);
+        if constexpr (FACE_ITEMS > NT) {
+            if (tid + NT < FACE_ITEMS) face_item(tid + NT);
         }
         __syncthreads();
         if (active) {
