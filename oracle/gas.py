@@ -142,6 +142,61 @@ def central_flux(qi, qj, gas: Gas):
 TWO_POINT = {0: chandrashekar_flux, 1: central_flux, 2: kennedy_gruber_flux, 3: central_flux}
 
 
+def matrix_dissipation_operator(qi, qn, nbar, gas: Gas):
+    """The 5x5 matrix |nbar| R |Lambda| T R^T of the entropy-stable matrix interface dissipation
+    (shape (5, 5, ...)): the dissipative part of a Roe-type flux written in entropy variables, with
+    the eigenvectors R of the flux Jacobian in the unit normal n = nbar/|nbar| scaled by T so that
+    R T R^T = dq/dw (the matrix-dissipation operators of Barth, Chandrashekar and Winters et al.),
+    and the states averaged as in the Chandrashekar flux:
+
+    rho_hat, beta_hat logarithmic means; beta_bar, U_bar, |U|^2_bar arithmetic means;
+    p_hat = rho_bar / (2 beta_bar);  a_hat = sqrt(gamma p_hat / rho_hat);
+    h_hat = gamma / (2 (gamma-1) beta_hat) + |U_bar|^2 - |U|^2_bar / 2;
+    acoustic  r = [1, U_bar -+ a_hat n, h_hat -+ a_hat U_bar.n],  |U_bar.n -+ a_hat|,  rho_hat/(2 gamma)
+    entropy   r = [1, U_bar, |U_bar|^2/2],                        |U_bar.n|,          rho_hat (gamma-1)/gamma
+    shear     r = [0, t, U_bar.t] for the two unit tangents t,   |U_bar.n|,          p_hat
+    (the shear pair is B^T (I - n n^T) B with B = [0 | I | U_bar], so no tangents are needed).
+    Our entropy variables are R times the standard ones, so the scaling enters divided by R.
+    """
+    ri, ui, Pi, Ti = primitives(qi, gas)
+    rn, un, Pn, Tn = primitives(qn, gas)
+    g, R = gas.gamma, gas.R
+    bi, bn = 1.0 / (2.0 * R * Ti), 1.0 / (2.0 * R * Tn)
+    rho_hat = log_mean(ri, rn)
+    beta_hat = log_mean(bi, bn)
+    beta_bar = 0.5 * (bi + bn)
+    ub = 0.5 * (ui + un)
+    kbar = 0.5 * ((ui * ui).sum(0) + (un * un).sum(0))
+    p_hat = 0.5 * (ri + rn) / (2.0 * beta_bar)
+    a_hat = np.sqrt(g * p_hat / rho_hat)
+    ubsq = (ub * ub).sum(0)
+    h_hat = g / (2.0 * (g - 1.0) * beta_hat) + ubsq - 0.5 * kbar
+    nn = np.sqrt((nbar * nbar).sum(0))
+    n = nbar / nn
+    vn = (ub * n).sum(0)
+    one, zero = np.ones_like(vn), np.zeros_like(vn)
+    M = np.zeros((5, 5) + vn.shape, dtype=np.result_type(vn, np.float64))
+    for sgn in (-1.0, 1.0):
+        r = np.stack([one, ub[0] + sgn * a_hat * n[0], ub[1] + sgn * a_hat * n[1],
+                      ub[2] + sgn * a_hat * n[2], h_hat + sgn * a_hat * vn])
+        M = M + (np.abs(vn + sgn * a_hat) * rho_hat / (2.0 * g * R)) * r[:, None] * r[None, :]
+    r = np.stack([one, ub[0], ub[1], ub[2], 0.5 * ubsq])
+    M = M + (np.abs(vn) * rho_hat * (g - 1.0) / (g * R)) * r[:, None] * r[None, :]
+    B = np.zeros((3, 5) + vn.shape, dtype=M.dtype)
+    for k in range(3):
+        B[k, k + 1] = one
+        B[k, 4] = ub[k]
+    P = np.stack([np.stack([(1.0 if i == j else 0.0) - n[i] * n[j] for j in range(3)]) for i in range(3)])
+    M = M + (np.abs(vn) * p_hat / R) * np.einsum("ka...,kl...,lb...->ab...", B, P, B)
+    return nn * M
+
+
+def matrix_dissipation(qi, qn, nbar, gas: Gas):
+    """|nbar| R |Lambda| T R^T (w_i - w_nu), shape (5, ...) (see matrix_dissipation_operator)."""
+    dw = entropy_variables(qi, gas) - entropy_variables(qn, gas)
+    return np.einsum("ab...,b...->a...", matrix_dissipation_operator(qi, qn, nbar, gas), dw)
+
+
 def contract(F, n):
     """sum_m F_m n_m for F of shape (3, 5, ...) and n of shape (3, ...)."""
     return F[0] * n[0] + F[1] * n[1] + F[2] * n[2]

@@ -13,7 +13,8 @@ are garbled or that defer to other papers:
   neighbour, n = (A_l,i + A_l,nu)/2, w_end the end weight of the 1-D norm:
       -(s / w_end) [ F#(q_i, q_nu) . n - F(q_i) . A_l,i ]
   plus local Lax-Friedrichs dissipation -(lam / (2 w_end)) (q_i - q_nu),
-  lam = max over the two sides of |U . n| + c |n|;
+  lam = max over the two sides of |U . n| + c |n| (iface_diss = 1), or the matrix dissipation
+  -(1 / (2 w_end)) |n| R |Lambda| T R^T (w_i - w_nu) (iface_diss = 2, ``gas.matrix_dissipation``);
 * viscous operator with theta_a = D_a w + (s/(2 w_end)) (w_nu - w_i) on faces of direction a,
   g_j = sum_a A_aj theta_a / J, F^V_m = sum_j C_mj g_j, fhat_l = sum_m A_lm F^V_m, and
       sum_l D_l fhat_l + (s/(2 w_end)) (fhat_l,nu - fhat_l,i)
@@ -35,8 +36,8 @@ from .geometry import apply_D
 
 
 class Params:
-    """Problem constants: the gas, interior-penalty coefficient eta, whether interface
-    dissipation is on, and the inviscid volume form: 0 Chandrashekar (ES-C), 1 central, 2
+    """Problem constants: the gas, interior-penalty coefficient eta, the interface dissipation
+    (0 none, 1 local Lax-Friedrichs, 2 entropy-stable matrix dissipation), and the inviscid volume form: 0 Chandrashekar (ES-C), 1 central, 2
     Kennedy-Gruber (SF-KG) two-point fluxes, or 3 the standard DC form."""
 
     def __init__(self, gamma=1.4, R=1.0, mu=0.0, Pr=0.72, eta=1.0, iface_diss=1, two_point=0):
@@ -125,7 +126,9 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
         An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
         nbar = 0.5 * (Ai + An)
         sat = -(s / w_end) * (G.contract(flux(qi, qn, gas), nbar) - G.contract(G.euler_flux(qi, gas), Ai))
-        if prm.iface_diss:
+        if prm.iface_diss == 2:
+            sat = sat - G.matrix_dissipation(qi, qn, nbar, gas) / (2.0 * w_end)
+        elif prm.iface_diss:
             nn = np.sqrt((nbar * nbar).sum(0))
 
             def speed(qx):
