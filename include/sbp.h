@@ -61,7 +61,9 @@ extern "C" {
  * conductivity kappa = mu c_p / Pr; mu == 0 evaluates the Euler residual only. */
 typedef struct sbp_problem {
     int32_t p;              /* polynomial degree, 1..SBP_MAX_P                                 */
-    int32_t iface_diss;     /* 1: local Lax-Friedrichs interface dissipation (entropy stable)  */
+    int32_t iface_diss;     /* interface dissipation: 0 none (entropy conservative), 1 local   */
+                            /* Lax-Friedrichs, 2 entropy-stable matrix dissipation             */
+                            /* |n| R|Lambda|T R^T (w_i - w_nu) (Roe-type, in entropy variables) */
     int64_t n_elem;         /* K > 0                                                           */
     const int32_t *nbr;     /* device [K][6]                                                   */
     const double *metric;   /* device SoA [9][K*N^3]                                           */
@@ -125,7 +127,8 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
  * element recomputing its forward intermediates (no two-point fluxes are stored) and interface
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
  * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0) on periodic problems
- * (bc_state == NULL); other fluxes or boundary data give SBP_ERR_ARG, degrees above SBP_MAX_VJP_P
+ * (bc_state == NULL) with iface_diss 0 or 1; other fluxes, boundary data or matrix dissipation give
+ * SBP_ERR_ARG, degrees above SBP_MAX_VJP_P
  * give SBP_ERR_DEGREE.  A source term does not enter the product.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
  * in the interface dissipation takes the own side on ties. */
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,

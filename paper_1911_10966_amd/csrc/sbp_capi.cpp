@@ -138,7 +138,7 @@ int check_problem(const sbp_problem &pr) {
     if (pr.mu > 0.0 && !(pr.Pr > 0.0)) return SBP_ERR_ARG;
     if (pr.two_point < 0 || pr.two_point > 3 || pr.reserved != 0) return SBP_ERR_ARG;
     if ((pr.bc_state && !aligned8(pr.bc_state)) || (pr.source && !aligned8(pr.source))) return SBP_ERR_ARG;
-    if (pr.iface_diss != 0 && pr.iface_diss != 1) return SBP_ERR_ARG;
+    if (pr.iface_diss < 0 || pr.iface_diss > 2) return SBP_ERR_ARG;
     return SBP_OK;
 }
 
@@ -520,7 +520,8 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
         return SBP_ERR_ARG;
     for (int b = 0; b < n_prob; ++b) {
-        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].bc_state != nullptr)
+        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].bc_state != nullptr ||
+            probs[b].iface_diss == 2)
             return SBP_ERR_ARG;
         if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
     }

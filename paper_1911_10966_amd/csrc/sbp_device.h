@@ -277,6 +277,77 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
     return a;
 }
 
+// Entropy-stable matrix interface dissipation |n| R |Lambda| T R^T (w_i - w_nu) for face states a
+// (own) and b (partner), n = (n0, n1, n2) the averaged metric row: the Roe-type dissipation in
+// entropy variables, eigenvectors of the flux Jacobian in n/|n| at the Chandrashekar-flux averages,
+// scaled so that R T R^T = dq/dw.  Both nodes carry their logarithms.
+__device__ __forceinline__ void matrix_dissipation(const Node &a, const Node &b, double n0, double n1,
+                                                   double n2, double gamma, double R, double out[5]) {
+    const double gm1 = gamma - 1.0;
+    // logarithmic means of rho and beta (series near equal states, as in the flux)
+    const double sr = a.rho + b.rho, dr = a.rho - b.rho;
+    const double sb = a.beta + b.beta, db = a.beta - b.beta;
+    const double irb = rcp(sr * sb);
+    const double isr = sb * irb, isb = sr * irb;
+    const double zr = dr * isr, ur = zr * zr;
+    const double rho_hat = ur < LOGMEAN_U ? 0.5 * sr * series_G(ur) : dr * rcp(a.lrho - b.lrho);
+    const double zb = db * isb, ub_ = zb * zb;
+    const double ibeta_hat = ub_ < LOGMEAN_U ? 2.0 * isb * series_F(ub_) : (a.lbeta - b.lbeta) * rcp(db);
+    const double p_hat = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
+    const double a_hat = sqrt(gamma * p_hat * rcp(rho_hat));
+    const double u1 = 0.5 * (a.u1 + b.u1), u2 = 0.5 * (a.u2 + b.u2), u3 = 0.5 * (a.u3 + b.u3);
+    const double ubsq = u1 * u1 + u2 * u2 + u3 * u3;
+    const double h_hat = 0.5 * gamma / gm1 * ibeta_hat + ubsq - 0.25 * (a.k + b.k);
+    const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    const double inn = rcp(nn);
+    const double e0 = n0 * inn, e1 = n1 * inn, e2 = n2 * inn;
+    const double vn = u1 * e0 + u2 * e1 + u3 * e2;
+    // entropy-variable jump (w_1 up to a constant that cancels)
+    const double R2 = 2.0 * R;
+    double dw[5];
+    dw[0] = R * ((a.lbeta - b.lbeta) / gm1 + (a.lrho - b.lrho) - (a.beta * a.k - b.beta * b.k));
+    dw[1] = R2 * (a.beta * a.u1 - b.beta * b.u1);
+    dw[2] = R2 * (a.beta * a.u2 - b.beta * b.u2);
+    dw[3] = R2 * (a.beta * a.u3 - b.beta * b.u3);
+    dw[4] = -R2 * (a.beta - b.beta);
+    const double iR = rcp(R);
+    // acoustic waves
+    const double ca = rho_hat * iR / (2.0 * gamma);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = 0.0;
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+        const double s = (double)sg;
+        const double r[5] = {1.0, fma(s * a_hat, e0, u1), fma(s * a_hat, e1, u2), fma(s * a_hat, e2, u3),
+                             fma(s * a_hat, vn, h_hat)};
+        const double proj = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
+        const double k = fabs(fma(s, a_hat, vn)) * ca * proj;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = fma(k, r[c], out[c]);
+    }
+    // entropy wave
+    {
+        const double r[5] = {1.0, u1, u2, u3, 0.5 * ubsq};
+        const double proj = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
+        const double k = fabs(vn) * rho_hat * gm1 / gamma * iR * proj;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = fma(k, r[c], out[c]);
+    }
+    // shear waves: (I - e e^T) acting on v = dw_U + U_bar dw_5
+    {
+        const double v0 = fma(u1, dw[4], dw[1]), v1 = fma(u2, dw[4], dw[2]), v2 = fma(u3, dw[4], dw[3]);
+        const double ve = v0 * e0 + v1 * e1 + v2 * e2;
+        const double t0 = v0 - ve * e0, t1 = v1 - ve * e1, t2 = v2 - ve * e2;
+        const double k = fabs(vn) * p_hat * iR;
+        out[1] = fma(k, t0, out[1]);
+        out[2] = fma(k, t1, out[2]);
+        out[3] = fma(k, t2, out[3]);
+        out[4] = fma(k, u1 * t0 + u2 * t1 + u3 * t2, out[4]);
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] *= nn;
+}
+
 // Data of the partner node of a face node: state, metric row of the face direction and, when the
 // interior penalty needs it, J.
 struct FaceNbr {
@@ -352,7 +423,16 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) v[c] = -s * isw * f[c];
-    if (a.iface_diss) {
+    if (a.iface_diss == 2) {
+        Node ob = o;  // the partner's logarithms were not needed by the flux's series branch
+        ob.lrho = log(o.rho);
+        ob.lbeta = log(o.beta);
+        double md[5];
+        matrix_dissipation(mi, ob, n0, n1, n2, a.gamma, a.R, md);
+        const double cf = -0.5 * isw;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[c] = fma(cf, md[c], v[c]);
+    } else if (a.iface_diss) {
         const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
         const double li = fabs(mi.u1 * n0 + mi.u2 * n1 + mi.u3 * n2) + ow.c * nn;
         const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;

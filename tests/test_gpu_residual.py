@@ -47,6 +47,11 @@ CASES = [
     (14, 2, 0.01, 1, 0, 0.1, 0.0),
     (15, 2, 0.01, 1, 0, 0.1, 1.0),
     (15, 2, 0.0, 0, 3, 0.1, 1.0),
+    # entropy-stable matrix interface dissipation
+    (3, 3, 0.02, 2, 0, 0.1, 1.0),
+    (4, 2, 0.0, 2, 2, 0.12, 1.0),
+    (6, 2, 0.0, 2, 0, 0.1, 1.0),
+    (11, 2, 0.01, 2, 0, 0.1, 1.0),
 ]
 
 
