@@ -63,7 +63,8 @@ typedef struct sbp_problem {
     int32_t p;              /* polynomial degree, 1..SBP_MAX_P                                 */
     int32_t iface_diss;     /* interface dissipation: 0 none (entropy conservative), 1 local   */
                             /* Lax-Friedrichs, 2 entropy-stable matrix dissipation             */
-                            /* |n| R|Lambda|T R^T (w_i - w_nu) (Roe-type, in entropy variables) */
+                            /* |n| R|Lambda|T R^T (w_i - w_nu) (Roe-type, in entropy variables; */
+                            /* with the Chandrashekar or Kennedy-Gruber flux, default schedule) */
     int64_t n_elem;         /* K > 0                                                           */
     const int32_t *nbr;     /* device [K][6]                                                   */
     const double *metric;   /* device SoA [9][K*N^3]                                           */

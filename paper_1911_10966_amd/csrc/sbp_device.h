@@ -400,7 +400,9 @@ __device__ __forceinline__ FaceOwn face_own(const ResArgs &a, const Node &m, dou
     return o;
 }
 
-template <int FLUX, bool VISC>
+// MD selects the matrix interface dissipation at compile time: its registers would otherwise be
+// reserved by every launch (iface_diss is uniform per problem group).
+template <int FLUX, bool VISC, bool MD = false>
 __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
                                            const FaceNbr &nb, double s, double v[9]) {
     const Node &mi = ow.m;
@@ -423,7 +425,7 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) v[c] = -s * isw * f[c];
-    if (a.iface_diss == 2) {
+    if constexpr (MD) {
         Node ob = o;  // the partner's logarithms were not needed by the flux's series branch
         ob.lrho = log(o.rho);
         ob.lbeta = log(o.beta);
@@ -461,12 +463,12 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
     }
 }
 
-template <int FLUX, bool VISC>
+template <int FLUX, bool VISC, bool MD = false>
 __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
                                            long long pg, bool bnd, int l, double s, double v[9]) {
     FaceNbr nb;
     load_face_nbr<VISC>(a, pg, bnd, l, nb);
-    face_terms<FLUX, VISC>(a, ow, Ai, nb, s, v);
+    face_terms<FLUX, VISC, MD>(a, ow, Ai, nb, s, v);
 }
 
 }  // namespace

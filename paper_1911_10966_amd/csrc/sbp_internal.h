@@ -87,13 +87,15 @@ struct Schedule {
 };
 int schedule_count(int p);
 Schedule schedule_of(int p, int variant);
-int launch_group_residual(int p, bool visc, int flux, int variant, const GroupArgs &g, hipStream_t s,
-                          bool fixup);
+// md: matrix interface dissipation (iface_diss = 2; default schedule, fluxes 0 and 2 only).
+int launch_group_residual(int p, bool visc, int flux, bool md, int variant, const GroupArgs &g,
+                          hipStream_t s, bool fixup);
 int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArgs &r, hipStream_t s);
 // Degrees whose elements exceed one workgroup (p >= 9) run as passes over node planes; a
 // schedule's `epw` is then the number of planes per workgroup.
 constexpr int kFirstPlaneP = 9;
-int launch_group_residual_planes(int p, int ppb, bool visc, int flux, const GroupArgs &g, hipStream_t s);
+int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, const GroupArgs &g,
+                                 hipStream_t s);
 int launch_metrics_big(int p, long long K, const double *x, double *metric, double *jac,
                        const double *D, hipStream_t s);
 

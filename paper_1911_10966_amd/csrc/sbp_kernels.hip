@@ -23,7 +23,8 @@ constexpr int tile_fields(bool visc) { return visc ? 24 : 20; }
 constexpr int kFaceItemsFrom = 6;
 
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
-template <int N, int EPW, bool VISC, int FLUX>
+// MD: matrix interface dissipation (iface_diss = 2) instead of Lax-Friedrichs.
+template <int N, int EPW, bool VISC, int FLUX, bool MD>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
                                               const double *s_D) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
@@ -242,7 +243,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 else mi.k = s_buf[F_K * NODES + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
                                        side ? 1.0 : -1.0, v);
             }
 #pragma unroll
@@ -287,7 +288,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 sfaces |= 1 << l;
                 const long long pg = kind == 1 ? nb * N3 + ln + (N - 1 - 2 * il) * stride[l] : g;
                 double v[9];
-                face_terms<FLUX, VISC>(a, own, A[l], pg, kind == 2, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC, MD>(a, own, A[l], pg, kind == 2, l, side ? 1.0 : -1.0, v);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {
@@ -406,7 +407,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
 // Residual over a group of problems.  Non-persistent: one block per element tile.  Persistent:
 // a grid sized to the resident capacity walks the tiles (the grid is a multiple of the XCD count,
 // so the XCD-contiguous remap of tile indices still holds).
-template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE>
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE, bool MD>
 __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
 __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
 k_residual(const GroupArgs g) {
@@ -418,13 +419,13 @@ k_residual(const GroupArgs g) {
         const long long vb = xcd_block(blockIdx.x, gridDim.x);
         const int b = find_problem(g.block_start, g.n, vb);
         const ResArgs a = problem_view(g, g.probs[b], g.out);
-        residual_tile<N, EPW, VISC, FLUX>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+        residual_tile<N, EPW, VISC, FLUX, MD>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
     } else {
         for (long long it = blockIdx.x; it < g.total_blocks; it += gridDim.x) {
             const long long vb = xcd_block(it, g.total_blocks);
             const int b = find_problem(g.block_start, g.n, vb);
             const ResArgs a = problem_view(g, g.probs[b], g.out);
-            residual_tile<N, EPW, VISC, FLUX>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+            residual_tile<N, EPW, VISC, FLUX, MD>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
             __syncthreads();
         }
     }
@@ -626,10 +627,10 @@ int device_cus() {
     return cus;
 }
 
-template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE = 0>
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE = 0, bool MD = false>
 int launch_res_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
-    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST, WPE>;
+    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST, WPE, MD>;
     long long grid = g.total_blocks;
     if (PERSIST) {
         static int per_cu = 0;
@@ -662,6 +663,18 @@ int launch_res_e(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
         case 1: return visc ? launch_res_k<N, EPW, true, 1, false>(g, s) : launch_res_k<N, EPW, false, 1, false>(g, s);
         case 2: return visc ? launch_res_k<N, EPW, true, 2, false>(g, s) : launch_res_k<N, EPW, false, 2, false>(g, s);
         case 3: return visc ? launch_res_k<N, EPW, true, 3, false>(g, s) : launch_res_k<N, EPW, false, 3, false>(g, s);
+        default: return -1;
+    }
+}
+
+// Matrix interface dissipation: default schedule, Chandrashekar and Kennedy-Gruber fluxes.
+template <int N, int EPW>
+int launch_res_md(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
+    switch (flux) {
+        case 0: return visc ? launch_res_k<N, EPW, true, 0, false, 0, true>(g, s)
+                            : launch_res_k<N, EPW, false, 0, false, 0, true>(g, s);
+        case 2: return visc ? launch_res_k<N, EPW, true, 2, false, 0, true>(g, s)
+                            : launch_res_k<N, EPW, false, 2, false, 0, true>(g, s);
         default: return -1;
     }
 }
@@ -712,16 +725,28 @@ Schedule schedule_of(int p, int v) {
     }
 }
 
-int launch_group_residual(int p, bool visc, int flux, int variant, const GroupArgs &g, hipStream_t s,
-                          bool fixup) {
+int launch_group_residual(int p, bool visc, int flux, bool md, int variant, const GroupArgs &g,
+                          hipStream_t s, bool fixup) {
     if (variant < 0 || variant >= schedule_count(p)) return -1;
-    if (flux != 0 && variant != 0) return -1;
+    if ((flux != 0 || md) && variant != 0) return -1;
     const Schedule sc = schedule_of(p, variant);
     // high degrees: plane passes, which finish SAT^V themselves (no fixup)
-    if (p >= kFirstPlaneP) return launch_group_residual_planes(p, sc.epw, visc, flux, g, s);
+    if (p >= kFirstPlaneP) return launch_group_residual_planes(p, sc.epw, visc, flux, md, g, s);
     int rc = -1;
     const bool P1 = sc.persistent != 0;
-    if (flux == 0) {
+    if (md) {
+        switch (p) {
+            case 1: rc = launch_res_md<2, 8>(visc, flux, g, s); break;
+            case 2: rc = launch_res_md<3, 2>(visc, flux, g, s); break;
+            case 3: rc = launch_res_md<4, 1>(visc, flux, g, s); break;
+            case 4: rc = launch_res_md<5, 1>(visc, flux, g, s); break;
+            case 5: rc = launch_res_md<6, 1>(visc, flux, g, s); break;
+            case 6: rc = launch_res_md<7, 1>(visc, flux, g, s); break;
+            case 7: rc = launch_res_md<8, 1>(visc, flux, g, s); break;
+            case 8: rc = launch_res_md<9, 1>(visc, flux, g, s); break;
+            default: return -1;
+        }
+    } else if (flux == 0) {
 #define SBP_CASE(NN, EE)                                                                \
     if (sc.epw == EE && sc.wpe == 0) rc = P1 ? launch_res_e0<NN, EE, true>(visc, g, s)  \
                                              : launch_res_e0<NN, EE, false>(visc, g, s);

@@ -157,7 +157,7 @@ __device__ __forceinline__ int plane_problem(const GroupArgs &g, long long &vb) 
 }
 
 // ---- pass A: planes of constant xi3 (directions xi1, xi2) -------------------------------------
-template <int N, int PPB, bool VISC, int FLUX>
+template <int N, int PPB, bool VISC, int FLUX, bool MD>
 __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs g) {
     constexpr int N2 = N * N, N3 = N2 * N, NODES = PPB * N2;
     constexpr int ITEMS = PPB * 4 * N;  // face nodes of the plane: 2 directions x 2 sides x N
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + j1 + N * j2);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
                                        side ? 1.0 : -1.0, v);
             }
         }
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
 }
 
 // ---- pass B: planes of constant xi2 (direction xi3) --------------------------------------------
-template <int N, int PPB, bool VISC, int FLUX>
+template <int N, int PPB, bool VISC, int FLUX, bool MD>
 __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs g) {
     constexpr int N2 = N * N, N3 = N2 * N, NODES = PPB * N2;
     constexpr int ITEMS = PPB * 2 * N;  // face nodes of the plane: 2 sides x N
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + t + N * il);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, 2,
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, 2,
                                        side ? 1.0 : -1.0, v);
             }
         }
@@ -612,14 +612,14 @@ k_metrics_big(const double *x, double *metric, double *jac, const double *D, lon
     }
 }
 
-template <int N, int PPB, bool VISC, int FLUX>
+template <int N, int PPB, bool VISC, int FLUX, bool MD>
 int launch_planes_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(PPB * N * N);
     const dim3 grid((unsigned)g.total_blocks);
     KernelTimer &tm = residual_timer();
     if (tm.enabled) hipEventRecord(tm.begin, s);
-    hipLaunchKernelGGL((k_plane_a<N, PPB, VISC, FLUX>), grid, dim3(NT), 0, s, g);
-    hipLaunchKernelGGL((k_plane_b<N, PPB, VISC, FLUX>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_plane_a<N, PPB, VISC, FLUX, MD>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_plane_b<N, PPB, VISC, FLUX, MD>), grid, dim3(NT), 0, s, g);
     if constexpr (VISC) hipLaunchKernelGGL((k_plane_c<N, PPB>), grid, dim3(NT), 0, s, g);
     if (hipGetLastError() != hipSuccess) return -1;
     if (tm.enabled) hipEventRecord(tm.end, s);
@@ -629,30 +629,42 @@ int launch_planes_k(const GroupArgs &g, hipStream_t s) {
 template <int N, int PPB>
 int launch_planes_f(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
     switch (flux) {
-        case 0: return visc ? launch_planes_k<N, PPB, true, 0>(g, s) : launch_planes_k<N, PPB, false, 0>(g, s);
-        case 1: return visc ? launch_planes_k<N, PPB, true, 1>(g, s) : launch_planes_k<N, PPB, false, 1>(g, s);
-        case 2: return visc ? launch_planes_k<N, PPB, true, 2>(g, s) : launch_planes_k<N, PPB, false, 2>(g, s);
-        case 3: return visc ? launch_planes_k<N, PPB, true, 3>(g, s) : launch_planes_k<N, PPB, false, 3>(g, s);
+        case 0: return visc ? launch_planes_k<N, PPB, true, 0, false>(g, s) : launch_planes_k<N, PPB, false, 0, false>(g, s);
+        case 1: return visc ? launch_planes_k<N, PPB, true, 1, false>(g, s) : launch_planes_k<N, PPB, false, 1, false>(g, s);
+        case 2: return visc ? launch_planes_k<N, PPB, true, 2, false>(g, s) : launch_planes_k<N, PPB, false, 2, false>(g, s);
+        case 3: return visc ? launch_planes_k<N, PPB, true, 3, false>(g, s) : launch_planes_k<N, PPB, false, 3, false>(g, s);
+        default: return -1;
+    }
+}
+
+// Matrix interface dissipation: one plane per workgroup, Chandrashekar and Kennedy-Gruber fluxes.
+template <int N>
+int launch_planes_md(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
+    switch (flux) {
+        case 0: return visc ? launch_planes_k<N, 1, true, 0, true>(g, s) : launch_planes_k<N, 1, false, 0, true>(g, s);
+        case 2: return visc ? launch_planes_k<N, 1, true, 2, true>(g, s) : launch_planes_k<N, 1, false, 2, true>(g, s);
         default: return -1;
     }
 }
 
 template <int N>
-int launch_planes_n(int ppb, bool visc, int flux, const GroupArgs &g, hipStream_t s) {
+int launch_planes_n(int ppb, bool visc, int flux, bool md, const GroupArgs &g, hipStream_t s) {
+    if (md) return ppb == 1 ? launch_planes_md<N>(visc, flux, g, s) : -1;
     return ppb == 2 ? launch_planes_f<N, 2>(visc, flux, g, s) : launch_planes_f<N, 1>(visc, flux, g, s);
 }
 
 }  // namespace
 
-int launch_group_residual_planes(int p, int ppb, bool visc, int flux, const GroupArgs &g, hipStream_t s) {
+int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, const GroupArgs &g,
+                                 hipStream_t s) {
     switch (p) {
-        case 9: return launch_planes_n<10>(ppb, visc, flux, g, s);
-        case 10: return launch_planes_n<11>(ppb, visc, flux, g, s);
-        case 11: return launch_planes_n<12>(ppb, visc, flux, g, s);
-        case 12: return launch_planes_n<13>(ppb, visc, flux, g, s);
-        case 13: return launch_planes_n<14>(ppb, visc, flux, g, s);
-        case 14: return launch_planes_n<15>(ppb, visc, flux, g, s);
-        case 15: return launch_planes_n<16>(ppb, visc, flux, g, s);
+        case 9: return launch_planes_n<10>(ppb, visc, flux, md, g, s);
+        case 10: return launch_planes_n<11>(ppb, visc, flux, md, g, s);
+        case 11: return launch_planes_n<12>(ppb, visc, flux, md, g, s);
+        case 12: return launch_planes_n<13>(ppb, visc, flux, md, g, s);
+        case 13: return launch_planes_n<14>(ppb, visc, flux, md, g, s);
+        case 14: return launch_planes_n<15>(ppb, visc, flux, md, g, s);
+        case 15: return launch_planes_n<16>(ppb, visc, flux, md, g, s);
         default: return -1;
     }
 }

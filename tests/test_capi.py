@@ -71,6 +71,9 @@ def test_argument_errors_on_host():
     assert L.sbp_residual(opt, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
     diss = (_lib.sbp_problem * 1)(_lib.sbp_problem(3, 3, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0))
     assert L.sbp_residual(diss, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
+    # matrix dissipation with the DC volume form is not offered
+    mdc = (_lib.sbp_problem * 1)(_lib.sbp_problem(3, 2, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 3, 0))
+    assert L.sbp_residual(mdc, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
     # misaligned boundary data
     bcm = (_lib.sbp_problem * 1)(_lib.sbp_problem(3, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0, 68, 0))
     assert L.sbp_residual(bcm, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG

@@ -50,6 +50,7 @@ CASES = [
     # entropy-stable matrix interface dissipation
     (3, 3, 0.02, 2, 0, 0.1, 1.0),
     (4, 2, 0.0, 2, 2, 0.12, 1.0),
+    (2, 3, 0.01, 2, 2, 0.1, 1.0),
     (6, 2, 0.0, 2, 0, 0.1, 1.0),
     (11, 2, 0.01, 2, 0, 0.1, 1.0),
 ]
