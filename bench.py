@@ -68,10 +68,10 @@ def algorithmic_bytes(p, K, viscous):
 # HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
 # this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
 # copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
-TRAFFIC = {"sha256": "83b2e02238610425e757cbc154416b6ec68bbabc5e0f0b843fc93b1cd5cfd7b8",
+TRAFFIC = {"sha256": "2ec9f17748a23c8cf1cf879a9080981dd76cecc3c875e2e9f5730f876fd08f5f",
            "workload": "ns_tgv_p4_e32",
            # bytes per launch by residual schedule index (degree 4)
-           "bytes": {0: 1360113144, 1: 1343264656, 2: 1049337040, 3: 1034077840, 4: 1358553544, 5: 1344933783, 6: 1296623497}}
+           "bytes": {0: 1311644648, 1: 1293414016, 2: 1036875144, 3: 1026171256, 4: 1271735238, 5: 1295126832, 6: 1308627095}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 
