@@ -574,8 +574,9 @@ def main():
     if not args.no_cpu_baseline:
         r = run_cpu_baseline(args.workload, args.cpu_sample)
         if r is not None:
+            which = ("all" if r["elems"] >= prob.K else "randomly chosen")
             cpu = {"value": round(r["value"], 4), "unit": UNIT, "cores": 1, "kind": "oracle",
-                   "sample": f"one residual of {r['elems']} randomly chosen elements "
+                   "sample": f"one residual of {r['elems']} {which} elements "
                              f"({r['nodes']} nodes) of {args.workload}, {r['seconds']:.1f} s"}
 
     line = {

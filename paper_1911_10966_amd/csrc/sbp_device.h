@@ -154,36 +154,6 @@ __device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, 
     }
 }
 
-// sum_m An_m F^V_m for the viscous flux of eq. Fv (Fourier heat flux) with stresses of eq. tau,
-// evaluated from entropy-variable gradients g[j][c] = dW_{c+1}/dx_j (c = 0..3: U/T and -1/T).
-// Returns the momentum and energy components (the mass component is zero).
-__device__ __forceinline__ void visc_flux_contract(const double g[3][4], double u1, double u2,
-                                                   double u3, double T, double mu, double kap,
-                                                   const double An[3], double out[4]) {
-    const double u[3] = {u1, u2, u3};
-    double du[3][3];  // du[k][j] = dU_k/dx_j = T (dW_{k+1}/dx_j + U_k dW_5/dx_j)
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) du[k][j] = T * fma(u[k], g[j][3], g[j][k]);
-    const double div = du[0][0] + du[1][1] + du[2][2];
-    const double T2k = kap * T * T;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) out[c] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        double tau[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            tau[i] = mu * (du[i][m] + du[m][i] - (i == m ? (2.0 / 3.0) * div : 0.0));
-        const double e = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + T2k * g[m][3];
-        out[0] = fma(An[m], tau[0], out[0]);
-        out[1] = fma(An[m], tau[1], out[1]);
-        out[2] = fma(An[m], tau[2], out[2]);
-        out[3] = fma(An[m], e, out[3]);
-    }
-}
-
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Map dispatch
 // slot b to a virtual block so that every XCD walks one contiguous range of elements: face
 // neighbours of an element are then mostly resident in the same L2.

@@ -99,16 +99,6 @@ int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, c
 int launch_metrics_big(int p, long long K, const double *x, double *metric, double *jac,
                        const double *D, hipStream_t s);
 
-// RK4 stage update, see launch_rk_stage.
-struct RkArgs {
-    double *q;
-    double *acc;
-    double *qs;
-    const double *k;
-    const double *dt;      // device scalar
-    long long n;           // number of doubles (5 * nodes)
-    int stage;
-};
 
 
 // Optional event timing of the main residual kernel (see sbp_profile in the C ABI).
@@ -117,7 +107,6 @@ struct KernelTimer {
     hipEvent_t begin = nullptr, end = nullptr;
 };
 KernelTimer &residual_timer();
-int launch_rk_stage(const RkArgs &a, hipStream_t s);
 
 // Vector-Jacobian product of the residual (Chandrashekar flux) for one problem.
 struct VjpArgs {

@@ -519,31 +519,6 @@ __global__ void __launch_bounds__(256) k_group_rk_stage(const GroupArgs g, const
     }
 }
 
-__global__ void __launch_bounds__(256) k_rk_stage(const RkArgs a) {
-    const double dt = *a.dt;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-        const double k = a.k[i];
-        const double q = a.q[i];
-        switch (a.stage) {
-            case 0:
-                a.acc[i] = fma(dt / 6.0, k, q);
-                a.qs[i] = fma(0.5 * dt, k, q);
-                break;
-            case 1:
-                a.acc[i] = fma(dt / 3.0, k, a.acc[i]);
-                a.qs[i] = fma(0.5 * dt, k, q);
-                break;
-            case 2:
-                a.acc[i] = fma(dt / 3.0, k, a.acc[i]);
-                a.qs[i] = fma(dt, k, q);
-                break;
-            default:
-                a.q[i] = fma(dt / 6.0, k, a.acc[i]);
-                break;
-        }
-    }
-}
 
 // Curl-form metrics J dxi_i/dx_n = -[curl_xi(X_l grad_xi X_m)]_i, (n, m, l) cyclic, and
 // J = det(dx/dxi), with every derivative the collocation derivative D along a line of the element.
@@ -817,12 +792,6 @@ KernelTimer &residual_timer() {
     return t;
 }
 
-int launch_rk_stage(const RkArgs &a, hipStream_t s) {
-    long long blocks = (a.n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_rk_stage, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
 
 int launch_metrics(int p, long long K, const double *x, double *metric, double *jac,
                    const double *D, hipStream_t s) {
