@@ -22,10 +22,21 @@ are garbled or that defer to other papers:
   Chat_ll = sum_{m,j} A_lm C_mj A_lj / J (eq. Chatij with the summation index fixed);
 * the output is dq/dt: the sum of the terms divided by J, plus an optional source term (the
   forcing of a manufactured solution, given per node);
-* a boundary face (neighbour index -1) is an interface with a ghost element whose face node
-  carries the prescribed (Dirichlet) state and the own node's metrics and J: the inviscid SAT,
-  dissipation, SAT^theta and interior penalty keep their interface form with the ghost data,
-  and SAT^V vanishes there (the boundary viscous flux is the interior one).
+* a boundary face is an interface with a ghost element whose face node carries a ghost state and
+  the own node's metrics and J; the inviscid SAT, dissipation, SAT^theta and interior penalty keep
+  their interface form with the ghost data.  The neighbour index names the boundary kind:
+  -1 Dirichlet: the ghost state is the prescribed state; SAT^V vanishes (the boundary viscous
+     flux is the interior one).  A far field is this kind with free-stream data.
+  -2 slip wall (inviscid problems only): the ghost is the own state with the momentum reflected
+     about the face, m - 2 (m . n) n with n the unit normal A_l / |A_l|; the shared flux then
+     carries the pressure alone.
+  -3 adiabatic no-slip wall: the ghost is the own state with the momentum reversed, (rho, -m,
+     rho E), so that the face averages hold zero velocity and the own temperature; the shared
+     flux carries the pressure alone, and SAT^V sets the boundary viscous flux to the own
+     momentum flux with zero energy flux (no heat flux, no work at rest):
+     -(s / w_end) fhat_l,i[energy] on the energy equation.
+  These wall terms follow from the entropy analysis of the interface terms (the wall SATs of the
+  references the paper cites are not given in it); the oracle's tests pin their entropy budget.
 """
 from __future__ import annotations
 
@@ -98,9 +109,13 @@ def volume_term(q, metric, sbp, prm: Params):
     return V
 
 
+DIRICHLET, SLIP_WALL, NOSLIP_WALL = -1, -2, -3
+
+
 def _partner(arr_all, nbr, elems, f, own, nb, l, bc_arr):
     """Face-node values of the partner across face f for the elements ``elems``: the neighbour's
-    mirrored face node, or, on boundary faces (neighbour -1), ``bc_arr`` at the own face node."""
+    mirrored face node, or, on boundary faces (negative neighbour index), ``bc_arr`` at the own
+    face node."""
     nb_e = nbr[elems, f]
     bnd = nb_e < 0
     out = _take(arr_all[..., np.where(bnd, elems, nb_e), :, :, :], nb, l)
@@ -111,9 +126,51 @@ def _partner(arr_all, nbr, elems, f, own, nb, l, bc_arr):
     return out
 
 
+def _slip_ghost(q, A):
+    """Own state with the momentum reflected about the face with normal direction A."""
+    mn = (q[1:4] * A).sum(0) / (A * A).sum(0)
+    g = q.copy()
+    g[1:4] = q[1:4] - 2.0 * mn * A
+    return g
+
+
+def _noslip_ghost(q):
+    """Own state with the momentum reversed."""
+    g = q.copy()
+    g[1:4] = -q[1:4]
+    return g
+
+
+def _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas):
+    """Partner state across face f (direction l) for the elements ``elems``: the neighbour's node,
+    or the ghost state of the boundary kind the neighbour index names."""
+    nb_e = nbr[elems, f]
+    bnd = nb_e < 0
+    qn = _take(q_all[:, np.where(bnd, elems, nb_e)], nb, l)
+    if not bnd.any():
+        return qn
+    qi = _take(q_all[:, elems], own, l)
+    Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
+    for code in np.unique(nb_e[bnd]):
+        sel = nb_e == code
+        if code == DIRICHLET:
+            if bc is None:
+                raise ValueError("Dirichlet boundary face without boundary data")
+            qn[:, sel] = _take(bc[:, elems[sel]], own, l)
+        elif code == SLIP_WALL:
+            if gas.mu != 0.0:
+                raise ValueError("slip walls are defined for inviscid problems only")
+            qn[:, sel] = _slip_ghost(qi[:, sel], Ai[:, sel])
+        elif code == NOSLIP_WALL:
+            qn[:, sel] = _noslip_ghost(qi[:, sel])
+        else:
+            raise ValueError(f"unknown boundary kind {code}")
+    return qn
+
+
 def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     """Interface SAT and local Lax-Friedrichs dissipation for the elements ``elems``; ``bc`` is
-    the Dirichlet state used on boundary faces."""
+    the state prescribed on Dirichlet boundary faces."""
     flux = G.TWO_POINT[prm.two_point]
     gas = prm.gas
     q = q_all[:, elems]
@@ -121,7 +178,7 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     w_end = sbp.w[0]
     for l, s, f, own, nb in _faces(sbp.p):
         qi = _take(q, own, l)
-        qn = _partner(q_all, nbr, elems, f, own, nb, l, bc)
+        qn = _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas)
         Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
         An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
         nbar = 0.5 * (Ai + An)
@@ -144,7 +201,7 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     return out
 
 
-def gradient_theta(q_all, nbr, elems, sbp, prm: Params, bc=None):
+def gradient_theta(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     """theta_a = D_a w + SAT^theta for the elements ``elems``, shape (3, 5, n, N, N, N)."""
     gas = prm.gas
     w = G.entropy_variables(q_all[:, elems], gas)
@@ -152,7 +209,7 @@ def gradient_theta(q_all, nbr, elems, sbp, prm: Params, bc=None):
     w_end = sbp.w[0]
     for a, s, f, own, nb in _faces(sbp.p):
         wi = _take(w, own, a)
-        wn = G.entropy_variables(_partner(q_all, nbr, elems, f, own, nb, a, bc), gas)
+        wn = G.entropy_variables(_partner_state(q_all, metric_all, nbr, elems, f, own, nb, a, bc, gas), gas)
         th[a][_index(w.ndim, own, a)] += (s / (2.0 * w_end)) * (wn - wi)
     return th
 
@@ -160,7 +217,7 @@ def gradient_theta(q_all, nbr, elems, sbp, prm: Params, bc=None):
 def contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None):
     """fhat_l = sum_m A_lm F^V_m with F^V_m = sum_j C_mj g_j and g_j = sum_a A_aj theta_a / J;
     shape (3, 5, n, N, N, N)."""
-    th = gradient_theta(q_all, nbr, elems, sbp, prm, bc)
+    th = gradient_theta(q_all, metric_all, nbr, elems, sbp, prm, bc)
     A = metric_all[:, elems]
     J = jac_all[elems]
     g = np.stack([sum(A[3 * a + j] * th[a] for a in range(3)) / J for j in range(3)])
@@ -195,9 +252,12 @@ def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=No
         fi = _take(fh[l], own, l)
         fn = _take(fh_ring[l][:, nb_pos], nb, l)
         sat_v = (s / (2.0 * w_end)) * (fn - fi)
-        sat_v[:, bnd] = 0.0   # no SAT^V on boundary faces
+        sat_v[:, bnd] = 0.0   # Dirichlet: the boundary viscous flux is the own one
+        wall = nb_e == NOSLIP_WALL
+        sat_v[4, wall] = -(s / w_end) * fi[4, wall]   # adiabatic wall: zero energy flux
         # interior penalty
-        qi, qn = _take(q, own, l), _partner(q_all, nbr, elems, f, own, nb, l, bc)
+        qi = _take(q, own, l)
+        qn = _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas)
         wi, wn = _take(w, own, l), G.entropy_variables(qn, gas)
         Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
         An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
@@ -214,8 +274,9 @@ def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chun
     """dq/dt for the elements ``elems`` (all by default), shape (5, n, N, N, N).
 
     ``chunk`` splits the element list into groups evaluated one after another (memory only).
-    ``bc`` (shape of q) holds the Dirichlet state read at the face nodes of boundary faces
-    (neighbour index -1); ``source`` (shape of q) is added to dq/dt.
+    ``bc`` (shape of q) holds the state read at the face nodes of Dirichlet boundary faces
+    (neighbour index -1; walls, -2 and -3, need no data); ``source`` (shape of q) is added to
+    dq/dt.
     """
     K = q_all.shape[1]
     if elems is None:

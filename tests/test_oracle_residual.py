@@ -101,7 +101,7 @@ def test_viscous_entropy_budget_identity():
     w = G.entropy_variables(q, gas)
     wj = c.weights3d() * c.jac
     lhs = (wj * (w * rv).sum(0)).sum()
-    th = R.gradient_theta(q, c.nbr, np.arange(c.prob.K), c.sbp, c.prm)
+    th = R.gradient_theta(q, c.metric, c.nbr, np.arange(c.prob.K), c.sbp, c.prm)
     g = np.stack([sum(c.metric[3 * a + j] * th[a] for a in range(3)) / c.jac for j in range(3)])
     vol = -(wj * (g * G.viscous_flux(q, g, gas)).sum(axis=(0, 1))).sum()
 

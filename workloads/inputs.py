@@ -43,6 +43,7 @@ class Problem:
     two_point: int = 0           # 0 -> Chandrashekar flux, 1 -> central (test only)
     init: str = "random"         # random | tgv | constant | vortex | shear | mms
     periodic: bool = True        # False: the six box faces are Dirichlet boundaries
+    box: Optional[tuple] = None  # per direction: None periodic, or a boundary kind (see neighbours)
     seed: int = 0
     Ma: float = 0.3
     u_rms: Optional[float] = None  # per-component rms velocity of the random state
@@ -94,6 +95,22 @@ def mms_problem(p: int, E: int, A: float = 0.0, two_point: int = 0, iface_diss: 
                    Re=mms.RE)
 
 
+def channel_problem(p: int, E: int, A: float = 0.0, iface_diss: int = 1,
+                    mu: Optional[float] = None, two_point: int = 0) -> Problem:
+    """The wall-bounded manufactured solution (``workloads.mms``, kind "channel") on the unit cube:
+    periodic in x_1 and x_3, adiabatic no-slip walls on the x_2 faces."""
+    from . import mms
+    return Problem(name=f"channel_p{p}_e{E}", p=p, E=E, L=1.0, A=A, gamma=mms.GAMMA,
+                   R=mms.CHANNEL_R, mu=mms.CHANNEL_MU if mu is None else mu, Pr=mms.PR,
+                   init="channel", box=(None, -3, None), two_point=two_point,
+                   iface_diss=iface_diss, Ma=0.3)
+
+
+def problem_neighbours(prob: Problem) -> np.ndarray:
+    """The neighbour table of a problem's box (periodic, Dirichlet or walls as it states)."""
+    return neighbours(prob.E, prob.periodic, prob.box)
+
+
 def config(name: str) -> Problem:
     """The single-problem workloads by name (the batch is ``batch_config``)."""
     if name == "euler_p3_e4":
@@ -132,23 +149,28 @@ def batch_config(n_prob: int = 256, seed_base: int = 4000, p_range=(2, 8), e_ran
 # ----------------------------------------------------------------------------------
 # Mesh
 # ----------------------------------------------------------------------------------
-def neighbours(E: int, periodic: bool = True) -> np.ndarray:
-    """[K, 6] int32 face-neighbour table of the E^3 grid: periodic wrap-around, or -1 on the faces
-    that lie on the box boundary."""
+def neighbours(E: int, periodic: bool = True, box=None) -> np.ndarray:
+    """[K, 6] int32 face-neighbour table of the E^3 grid.
+
+    ``box`` = (k1, k2, k3) says per direction what lies beyond the two box faces normal to it:
+    None for periodic wrap-around, or a negative boundary kind written into the table (-1
+    Dirichlet, -2 slip wall, -3 adiabatic no-slip wall).  ``periodic=False`` without ``box``
+    makes every box face a Dirichlet boundary."""
+    if box is None:
+        box = (None, None, None) if periodic else (-1, -1, -1)
     e = np.arange(E ** 3)
-    e1, e2, e3 = e % E, (e // E) % E, e // (E * E)
-
-    def idx(a, b, c):
-        n = (a % E) + E * (b % E) + E * E * (c % E)
-        if not periodic:
-            out = (a < 0) | (a >= E) | (b < 0) | (b >= E) | (c < 0) | (c >= E)
-            n = np.where(out, -1, n)
-        return n
-
-    nb = np.stack([idx(e1 - 1, e2, e3), idx(e1 + 1, e2, e3),
-                   idx(e1, e2 - 1, e3), idx(e1, e2 + 1, e3),
-                   idx(e1, e2, e3 - 1), idx(e1, e2, e3 + 1)], axis=1)
-    return nb.astype(np.int32)
+    pos = (e % E, (e // E) % E, e // (E * E))
+    cols = []
+    for d in range(3):
+        for step in (-1, 1):
+            c = [pos[0], pos[1], pos[2]]
+            c[d] = c[d] + step
+            n = (c[0] % E) + E * (c[1] % E) + E * E * (c[2] % E)
+            if box[d] is not None:
+                out = (c[d] < 0) | (c[d] >= E)
+                n = np.where(out, int(box[d]), n)
+            cols.append(n)
+    return np.stack(cols, axis=1).astype(np.int32)
 
 
 def coords(prob: Problem, xi1d, device="cpu") -> torch.Tensor:
@@ -247,9 +269,9 @@ def primitive_state(prob: Problem, x: torch.Tensor):
         T = torch.ones_like(x1)
         p = rho * prob.R * T
         return rho, u, p
-    if prob.init == "mms":
+    if prob.init in ("mms", "channel"):
         from . import mms
-        rho, u, p = mms.primitives(x)
+        rho, u, p = mms.primitives(x, "table" if prob.init == "mms" else "channel")
         return (torch.as_tensor(rho, dtype=F64, device=x.device), torch.as_tensor(u, dtype=F64, device=x.device),
                 torch.as_tensor(p, dtype=F64, device=x.device))
     if prob.init == "constant":

@@ -1,8 +1,14 @@
-"""Manufactured solution of the viscous error-vs-cost study (section "Viscous flow: 3D manufactured
-solution", eq. mms with the constants of Table tab_3dmms_ns): a supersonic steady flow on the unit
-cube with Dirichlet data on every face.
+"""Manufactured solutions: problem data (exact fields and the forcing that makes them steady).
 
-The exact primitive fields are sums of one-dimensional sines and cosines. The forcing that makes
+``kind="table"``: the supersonic flow of the viscous error-vs-cost study (section "Viscous flow:
+3D manufactured solution", eq. mms with the constants of Table tab_3dmms_ns) on the unit cube with
+Dirichlet data on every face.
+
+``kind="channel"``: a subsonic flow on the unit cube, periodic in x_1 and x_3, between the planes
+x_2 = 0 and x_2 = 1 on which the velocity and the normal temperature gradient vanish: the data of
+adiabatic no-slip walls there (this one is not from the paper; it exercises the wall boundaries).
+
+The exact primitive fields are sums and products of sines and cosines. The forcing that makes
 them a steady solution of the compressible Navier-Stokes equations,
 
     S = d F_m / d x_m - d F^V_m / d x_m,
@@ -51,12 +57,35 @@ def _field_expr(name, X):
     return e
 
 
-@functools.lru_cache(maxsize=None)
-def _symbolic(mu: float, gamma: float, Pr: float, R: float):
-    X = sp.symbols("x1 x2 x3", real=True)
+# channel solution: R = 1, T_0 = 1 (c_0 = 1.18), velocities up to 0.36, mu = 0.01
+CHANNEL_R = 1.0
+CHANNEL_MU = 0.01
+
+
+def _table_fields(X, R):
     rho = _field_expr("rho", X)
     U = [_field_expr(n, X) for n in ("u1", "u2", "u3")]
-    P = _field_expr("p", X)
+    return rho, U, _field_expr("p", X)
+
+
+def _channel_fields(X, R):
+    s, c, pi = sp.sin, sp.cos, sp.pi
+    x1, x2, x3 = X
+    rho = 1 + sp.Rational(1, 10) * s(2 * pi * x1) * s(2 * pi * x3) + sp.Rational(1, 20) * c(pi * x2)
+    U = [sp.Rational(3, 10) * s(pi * x2) * (1 + sp.Rational(1, 5) * c(2 * pi * x1)),
+         sp.Rational(1, 10) * s(pi * x2) ** 2 * s(2 * pi * x1),
+         sp.Rational(1, 5) * s(pi * x2) * c(2 * pi * x3)]
+    T = 1 + sp.Rational(1, 10) * c(pi * x2) + sp.Rational(1, 20) * s(2 * pi * x1) * c(2 * pi * x3)
+    return rho, U, rho * R * T
+
+
+_FIELDS = {"table": _table_fields, "channel": _channel_fields}
+
+
+@functools.lru_cache(maxsize=None)
+def _symbolic(kind: str, mu: float, gamma: float, Pr: float, R: float):
+    X = sp.symbols("x1 x2 x3", real=True)
+    rho, U, P = _FIELDS[kind](X, R)
     T = P / (rho * R)
     rhoE = P / (gamma - 1) + rho * (U[0] ** 2 + U[1] ** 2 + U[2] ** 2) / 2
     kappa = mu * gamma * R / ((gamma - 1) * Pr)
@@ -79,33 +108,41 @@ def _as_np(x):
     return x.detach().cpu().numpy() if isinstance(x, torch.Tensor) else np.asarray(x)
 
 
-def primitives(x):
+def _defaults(kind, mu, R):
+    if kind == "table":
+        return (MU if mu is None else mu), (R_GAS if R is None else R)
+    return (CHANNEL_MU if mu is None else mu), (CHANNEL_R if R is None else R)
+
+
+def primitives(x, kind="table", R=None):
     """(rho, U (3,...), P) of the manufactured solution at coordinates x (3, ...)."""
-    f_prim, _ = _symbolic(MU, GAMMA, PR, R_GAS)
+    mu, R = _defaults(kind, None, R)
+    f_prim, _ = _symbolic(kind, mu, GAMMA, PR, R)
     xn = _as_np(x)
     vals = [np.array(np.broadcast_to(np.asarray(v, dtype=np.float64), xn.shape[1:]))
             for v in f_prim(xn[0], xn[1], xn[2])]
     return vals[0], np.stack(vals[1:4]), vals[4]
 
 
-def conservative(x, gamma=GAMMA) -> np.ndarray:
+def conservative(x, gamma=GAMMA, kind="table", R=None) -> np.ndarray:
     """q = [rho, rho U, rho E] of the manufactured solution, shape (5, ...)."""
-    rho, u, p = primitives(x)
+    rho, u, p = primitives(x, kind, R)
     return np.stack([rho, rho * u[0], rho * u[1], rho * u[2],
                      p / (gamma - 1.0) + 0.5 * rho * (u * u).sum(0)])
 
 
-def source(x, mu=MU, gamma=GAMMA, Pr=PR, R=R_GAS) -> np.ndarray:
+def source(x, mu=None, gamma=GAMMA, Pr=PR, R=None, kind="table") -> np.ndarray:
     """Forcing S (5, ...) that makes the manufactured solution steady."""
-    _, f_src = _symbolic(mu, gamma, Pr, R)
+    mu, R = _defaults(kind, mu, R)
+    _, f_src = _symbolic(kind, mu, gamma, Pr, R)
     xn = _as_np(x)
     return np.stack([np.broadcast_to(np.asarray(v, dtype=np.float64), xn.shape[1:])
                      for v in f_src(xn[0], xn[1], xn[2])])
 
 
-def speed_max() -> float:
+def speed_max(kind="table") -> float:
     """An upper bound of |U| + c over the unit cube (for time-step selection)."""
     g = np.linspace(0.0, 1.0, 41)
     x = np.stack(np.meshgrid(g, g, g, indexing="ij"))
-    rho, u, p = primitives(x)
+    rho, u, p = primitives(x, kind)
     return float((np.sqrt((u * u).sum(0)) + np.sqrt(GAMMA * p / rho)).max())
