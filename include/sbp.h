@@ -18,7 +18,9 @@
  *   conservation law (eq. discGCLconvection); sbp_metrics() produces such metrics (curl form).
  * - nbr: [K][6] int32, face f = 2*l + s (s = 0 for the xi_l = -1 face, 1 for xi_l = +1) of element e
  *   touches element nbr[e*6 + f]; faces are conforming and aligned (the neighbour's opposite face,
- *   same tangential node indices).  Periodic grids list wrap-around neighbours.
+ *   same tangential node indices).  Periodic grids list wrap-around neighbours.  A negative entry
+ *   makes the face a boundary face of the kind it names (SBP_BC_*, below); any other entry outside
+ *   [0, K) is a mesh error (sticky flag, SBP_ERR_MESH from sbp_status()).
  * - Pointers marked "device" are HIP device allocations owned by the caller; the library never
  *   frees them and keeps no reference after the call returns (stream-ordered work may still read
  *   them until the stream reaches that point).  All device arrays must be 8-byte aligned.
@@ -74,16 +76,32 @@ typedef struct sbp_problem {
     int32_t two_point;      /* SBP_FLUX_*: inviscid volume form and interface flux            */
     int32_t reserved;       /* must be 0                                                       */
     /* Optional device SoA [5][K*N^3] arrays (NULL = absent):
-     * bc_state: prescribed (Dirichlet) state.  A face with nbr == -1 is then a boundary face: its
-     *   partner is a ghost node carrying bc_state at the own face node, with the own node's metrics
-     *   and J; the inviscid SAT, dissipation, SAT^theta and interior penalty keep their interface
-     *   form with that partner, and SAT^V vanishes (the boundary viscous flux is the interior one).
-     *   Only the entries at face nodes of boundary faces are read.  Without bc_state, nbr == -1 is
-     *   a mesh error like any other index outside [0, K).
+     * bc_state: prescribed state of SBP_BC_DIRICHLET faces; only the entries at their face nodes
+     *   are read.  Without bc_state, nbr == SBP_BC_DIRICHLET is a mesh error.
      * source: forcing added to dq/dt (e.g. of a manufactured solution). */
     const double *bc_state;
     const double *source;
 } sbp_problem;
+
+/* Boundary kinds, written into nbr in place of a neighbour index.  A boundary face node's partner
+ * is a ghost node with the own node's metrics and J; the inviscid SAT, interface dissipation,
+ * SAT^theta and interior penalty keep their interface form with that partner (the boundary SATs
+ * of the references the paper names for walls and far fields are not given in it; these forms are
+ * entropy stable, see each kind).
+ * SBP_BC_DIRICHLET: the ghost carries bc_state; SAT^V vanishes (the boundary viscous flux is the
+ *   own one).  A far field is this kind with free-stream data.
+ * SBP_BC_SLIP_WALL (inviscid problems only; with mu > 0 a mesh error): the ghost is the own state
+ *   with the momentum reflected about the face, m - 2 (m.n) n, n = A_l/|A_l|.  The shared flux
+ *   then carries the pressure alone, the wall produces no entropy with iface_diss 0, and the
+ *   dissipation acts on the normal momentum.
+ * SBP_BC_ADIABATIC_WALL: no-slip wall with no heat flux.  The ghost is the own state with the
+ *   momentum reversed (zero velocity and the own temperature on average); SAT^V is
+ *   -(s / w_end) fhat_l,i on the energy equation only (the wall does no work and passes no heat).
+ *   Mass and energy are conserved exactly, and the wall's entropy terms are the dissipation and
+ *   the interior penalty alone. */
+#define SBP_BC_DIRICHLET (-1)
+#define SBP_BC_SLIP_WALL (-2)
+#define SBP_BC_ADIABATIC_WALL (-3)
 
 /* Library version, for diagnostics. */
 int sbp_version(void);
@@ -129,7 +147,8 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
  * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0) on periodic problems
  * (bc_state == NULL) with iface_diss 0 or 1; other fluxes, boundary data or matrix dissipation give
- * SBP_ERR_ARG, degrees above SBP_MAX_VJP_P
+ * SBP_ERR_ARG; a boundary face in nbr (any negative entry) raises the mesh flag (SBP_ERR_MESH
+ * from sbp_status()) and its terms are left out; degrees above SBP_MAX_VJP_P
  * give SBP_ERR_DEGREE.  A source term does not enter the product.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
  * in the interface dissipation takes the own side on ties. */
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,

@@ -15,6 +15,9 @@ SBP_ERR_HIP = -5
 SBP_ERR_WORKSPACE = -6
 SBP_MAX_P = 15
 SBP_MAX_VJP_P = 8
+SBP_BC_DIRICHLET = -1
+SBP_BC_SLIP_WALL = -2
+SBP_BC_ADIABATIC_WALL = -3
 
 EXPORTED = ("sbp_version", "sbp_error_string", "sbp_lgl_operator", "sbp_metrics",
             "sbp_workspace_bytes", "sbp_residual", "sbp_rk_step", "sbp_residual_vjp",

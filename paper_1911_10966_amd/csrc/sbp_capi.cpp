@@ -431,7 +431,7 @@ int record_rk_graph(Plan *plan, double *q, const double *dt, char *ws, const Lay
 
 extern "C" {
 
-int sbp_version(void) { return 110; }
+int sbp_version(void) { return 111; }
 
 const char *sbp_error_string(int code) {
     switch (code) {

@@ -326,25 +326,45 @@ struct FaceNbr {
     double J;
 };
 
-// Kind of the face across which an element sees neighbour index nb: 1 interior (a valid
-// neighbour), 2 boundary (nb == -1 with boundary data present), 0 invalid (a mesh error).
+// Kind of the face across which an element sees neighbour index nb.
+enum FaceKind : int {
+    FACE_INVALID = 0,    // a mesh error
+    FACE_INTERIOR = 1,   // a valid neighbour
+    FACE_DIRICHLET = 2,  // nb == -1 with boundary data present
+    FACE_SLIP = 3,       // nb == -2 on an inviscid problem
+    FACE_WALL = 4,       // nb == -3: adiabatic no-slip wall
+};
+
 __device__ __forceinline__ int face_kind(const ResArgs &a, long long nb) {
-    if (nb >= 0 && nb < a.K) return 1;
-    return (nb == -1 && a.bc != nullptr) ? 2 : 0;
+    if (nb >= 0 && nb < a.K) return FACE_INTERIOR;
+    if (nb == -1) return a.bc != nullptr ? FACE_DIRICHLET : FACE_INVALID;
+    if (nb == -2) return a.mu == 0.0 ? FACE_SLIP : FACE_INVALID;
+    return nb == -3 ? FACE_WALL : FACE_INVALID;
 }
 
-// Partner of a face node: node pg of the neighbour, or on a boundary face (bnd) a ghost at the
-// own node pg carrying the prescribed state with the own metrics and J.
+// Partner of a face node: node pg of the neighbour or, on a boundary face, a ghost at the own node
+// pg with the own metrics and J carrying the prescribed state (Dirichlet), the own state with the
+// momentum reflected about the face (slip wall), or the own state with the momentum reversed
+// (no-slip wall: zero velocity and the own temperature on average).
 template <bool VISC>
-__device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, bool bnd, int l,
+__device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, int kind, int l,
                                               FaceNbr &n) {
     const long long nodes = a.nodes;
-    const double *qs = bnd ? a.bc : a.q;
+    const double *qs = kind == FACE_DIRICHLET ? a.bc : a.q;
 #pragma unroll
     for (int c = 0; c < 5; ++c) n.q[c] = qs[c * nodes + pg];
 #pragma unroll
     for (int m = 0; m < 3; ++m) n.A[m] = a.metric[(3 * l + m) * nodes + pg];
     n.J = (VISC && a.eta != 0.0) ? a.jac[pg] : 1.0;
+    if (kind == FACE_SLIP) {
+        const double mn = (n.q[1] * n.A[0] + n.q[2] * n.A[1] + n.q[3] * n.A[2]) *
+                          rcp(n.A[0] * n.A[0] + n.A[1] * n.A[1] + n.A[2] * n.A[2]);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) n.q[1 + m] = fma(-2.0 * mn, n.A[m], n.q[1 + m]);
+    } else if (kind == FACE_WALL) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) n.q[1 + m] = -n.q[1 + m];
+    }
 }
 
 // Interface terms at one face node i of face (l, s) with partner data nb: the EC shared flux
@@ -435,9 +455,9 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
 
 template <int FLUX, bool VISC, bool MD = false>
 __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
-                                           long long pg, bool bnd, int l, double s, double v[9]) {
+                                           long long pg, int kind, int l, double s, double v[9]) {
     FaceNbr nb;
-    load_face_nbr<VISC>(a, pg, bnd, l, nb);
+    load_face_nbr<VISC>(a, pg, kind, l, nb);
     face_terms<FLUX, VISC, MD>(a, ow, Ai, nb, s, v);
 }
 

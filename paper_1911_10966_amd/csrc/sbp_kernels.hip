@@ -190,7 +190,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     // The SAT^theta increments stay in LDS until the gradient phase (fields 8.. are free after the
     // pair loop): in the face slots for N >= 6, in per-node fields 8 + 4 l + c otherwise.
     // `faces` marks the node's interior faces (SAT^V), `sfaces` interior and boundary faces.
-    int faces = 0, sfaces = 0;
+    int faces = 0, sfaces = 0, wfaces = 0;  // interior, all valid, no-slip wall faces
     if constexpr (N >= kFaceItemsFrom) {
         // (face, face node) work items spread over all lanes: only 6/N of the nodes lie on a face
         // of a given direction, so a per-node loop over directions would leave most lanes idle.
@@ -225,7 +225,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int sl = l == 0 ? 1 : (l == 1 ? N : N2);
                 const int pl = es * N3 + lno;
                 const long long go = ee * N3 + lno;
-                const long long pg = kind == 1 ? nb * N3 + lno + (N - 1 - 2 * il) * sl : go;
+                const long long pg = kind == FACE_INTERIOR ? nb * N3 + lno + (N - 1 - 2 * il) * sl : go;
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -243,7 +243,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 else mi.k = s_buf[F_K * NODES + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, l,
                                        side ? 1.0 : -1.0, v);
             }
 #pragma unroll
@@ -261,8 +261,9 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 if (il != 0 && il != N - 1) continue;
                 const int side = (il == N - 1) ? 1 : 0;
                 const int kind = face_kind(a, a.nbr[e * 6 + 2 * l + side]);
-                if (kind == 0) continue;
-                if (kind == 1) faces |= 1 << l;
+                if (kind == FACE_INVALID) continue;
+                if (kind == FACE_INTERIOR) faces |= 1 << l;
+                if (kind == FACE_WALL) wfaces |= 1 << l;
                 sfaces |= 1 << l;
                 const int it = (slot * 6 + 2 * l + side) * N2 + tangential_index<N>(l, i1, i2, i3);
 #pragma unroll
@@ -284,11 +285,12 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     atomicOr(a.status, FLAG_MESH);
                     continue;
                 }
-                if (kind == 1) faces |= 1 << l;
+                if (kind == FACE_INTERIOR) faces |= 1 << l;
+                if (kind == FACE_WALL) wfaces |= 1 << l;
                 sfaces |= 1 << l;
-                const long long pg = kind == 1 ? nb * N3 + ln + (N - 1 - 2 * il) * stride[l] : g;
+                const long long pg = kind == FACE_INTERIOR ? nb * N3 + ln + (N - 1 - 2 * il) * stride[l] : g;
                 double v[9];
-                face_terms<FLUX, VISC, MD>(a, own, A[l], pg, kind == 2, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC, MD>(a, own, A[l], pg, kind, l, side ? 1.0 : -1.0, v);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {
@@ -369,6 +371,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     const double cs = -0.5 * (side ? 1.0 : -1.0) * isw;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cs, fh[l][c], acc[c + 1]);
+                } else if (wfaces & (1 << l)) {
+                    // adiabatic wall: the boundary viscous flux keeps the own momentum part and
+                    // has no energy part
+                    acc[4] = fma(-(side ? 1.0 : -1.0) * isw, fh[l][3], acc[4]);
                 }
             }
         }

@@ -221,14 +221,14 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
             const int j3 = (int)(ipl - e * N);
             const long long nb = a.nbr[e * 6 + f];
             const int kind = face_kind(a, nb);
-            if (kind == 0) {
+            if (kind == FACE_INVALID) {
                 atomicOr(a.status, FLAG_MESH);
             } else {
                 const int il = side ? N - 1 : 0;
                 const int j1 = l == 0 ? il : t, j2 = l == 0 ? t : il;
                 const int lno = j1 + N * j2 + N2 * j3;
                 const long long go = e * N3 + lno;
-                const long long pg = kind == 1 ? nb * N3 + lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N) : go;
+                const long long pg = kind == FACE_INTERIOR ? nb * N3 + lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N) : go;
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + j1 + N * j2);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, l,
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, l,
                                        side ? 1.0 : -1.0, v);
             }
         }
@@ -355,13 +355,13 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
             const int j2 = (int)(ipl - ee * N);
             const long long nb = a.nbr[ee * 6 + 4 + side];
             const int kind = face_kind(a, nb);
-            if (kind == 0) {
+            if (kind == FACE_INVALID) {
                 atomicOr(a.status, FLAG_MESH);
             } else {
                 const int il = side ? N - 1 : 0;
                 const int lno = t + N * j2 + N2 * il;
                 const long long go = ee * N3 + lno;
-                const long long pg = kind == 1 ? nb * N3 + lno + (N - 1 - 2 * il) * N2 : go;
+                const long long pg = kind == FACE_INTERIOR ? nb * N3 + lno + (N - 1 - 2 * il) * N2 : go;
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + t + N * il);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind == 2, 2,
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, 2,
                                        side ? 1.0 : -1.0, v);
             }
         }
@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
     }
     __syncthreads();
     double th2[4] = {0.0, 0.0, 0.0, 0.0};
-    bool face3 = false;
+    bool face3 = false, wall3 = false;
     const int side3 = i3 == N - 1 ? 1 : 0;
     if (on && (i3 == 0 || i3 == N - 1)) {
         const int it = pp * 2 * N + side3 * N + i1;
@@ -391,6 +391,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
         }
         const long long nb = a.nbr[e * 6 + 4 + side3];
         face3 = nb >= 0 && nb < a.K;
+        wall3 = face_kind(a, nb) == FACE_WALL;
     }
     if (on) {
 #pragma unroll
@@ -450,6 +451,9 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                     const double cs = -0.5 * (side3 ? 1.0 : -1.0) * a.isw;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc[c + 1] = fma(cs, fh[2][c], acc[c + 1]);
+                } else if (wall3) {
+                    // adiabatic wall: no energy part in the boundary viscous flux
+                    acc[4] = fma(-(side3 ? 1.0 : -1.0) * a.isw, fh[2][3], acc[4]);
                 }
             }
         }
@@ -528,7 +532,12 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_c(const GroupArgs 
         if (il != 0 && il != N - 1) continue;
         const int side = il == N - 1 ? 1 : 0;
         const long long nb = a.nbr[e * 6 + 2 * l + side];
-        if (nb < 0 || nb >= a.K) continue;
+        if (nb < 0 || nb >= a.K) {
+            // adiabatic wall across a xi1 or xi2 face (xi3 walls are done in pass B)
+            if (l < 2 && face_kind(a, nb) == FACE_WALL)
+                acc[3] = fma(-(side ? 1.0 : -1.0) * a.isw, fh[l][3], acc[3]);
+            continue;
+        }
         const double cs = 0.5 * (side ? 1.0 : -1.0) * a.isw;
         if (l < 2) {
             const long long pg = nb * N3 + (gn - e * N3) + (N - 1 - 2 * il) * lstride[l];

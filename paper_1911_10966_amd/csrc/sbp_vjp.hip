@@ -359,7 +359,10 @@ k_vjp_visc(const VjpArgs a) {
             const int side = (il == N - 1) ? 1 : 0;
             const double s = side ? 1.0 : -1.0;
             const long long nb = a.nbr[e * 6 + 2 * d + side];
-            if (nb < 0 || nb >= a.K) continue;
+            if (nb < 0 || nb >= a.K) {
+                atomicOr(a.status, FLAG_MESH);  // boundary faces are not differentiated
+                continue;
+            }
             const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
             NodeFull o;
             load_node(a.q, nodes, pg, gm1, a.R, o);
@@ -553,7 +556,10 @@ k_vjp_main(const VjpArgs a) {
             const int side = (il == N - 1) ? 1 : 0;
             const double s = side ? 1.0 : -1.0;
             const long long nb = a.nbr[e * 6 + 2 * l + side];
-            if (nb < 0 || nb >= a.K) continue;
+            if (nb < 0 || nb >= a.K) {
+                atomicOr(a.status, FLAG_MESH);  // boundary faces are not differentiated
+                continue;
+            }
             const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
             double qn[5], rbn[5];
             const double iJn = rcp(a.jac[pg]);
