@@ -37,6 +37,14 @@ are garbled or that defer to other papers:
      -(s / w_end) fhat_l,i[energy] on the energy equation.
   These wall terms follow from the entropy analysis of the interface terms (the wall SATs of the
   references the paper cites are not given in it); the oracle's tests pin their entropy budget.
+* faces of neighbouring elements may meet in any of the eight relative orientations of a square
+  (unstructured hexahedral meshes): ``orient[e, f] = f' + 8 * code`` names the neighbour's face f'
+  (direction l', side s') and how its face-node grid lies on the own one.  With own face-node
+  coordinates (a, b) (the two tangential indices in increasing direction order), the partner node
+  has (a', b') = (F_a(x), F_b(y)) with (x, y) = (b, a) if bit 0 of code is set, else (a, b), and
+  F_a, F_b reversals (N - 1 - .) when bits 1, 2 are set.  The partner's metric row and viscous
+  flux are those of its direction l', times -s s' (so that they point as the own direction l
+  does).  ``orient=None`` is the aligned case f' = f xor 1, code 0.
 """
 from __future__ import annotations
 
@@ -112,18 +120,59 @@ def volume_term(q, metric, sbp, prm: Params):
 DIRICHLET, SLIP_WALL, NOSLIP_WALL = -1, -2, -3
 
 
-def _partner(arr_all, nbr, elems, f, own, nb, l, bc_arr):
-    """Face-node values of the partner across face f for the elements ``elems``: the neighbour's
-    mirrored face node, or, on boundary faces (negative neighbour index), ``bc_arr`` at the own
-    face node."""
+def _face_links(nbr, orient, elems, f):
+    """Neighbour element, neighbour face f' and orientation code across face f of ``elems``."""
     nb_e = nbr[elems, f]
-    bnd = nb_e < 0
-    out = _take(arr_all[..., np.where(bnd, elems, nb_e), :, :, :], nb, l)
-    if bnd.any():
-        if bc_arr is None:
-            raise ValueError("boundary face without boundary data")
-        out[..., bnd, :, :] = _take(bc_arr[..., elems[bnd], :, :, :], own, l)
+    if orient is None:
+        return nb_e, np.full(nb_e.shape, f ^ 1), np.zeros(nb_e.shape, dtype=int)
+    o = orient[elems, f]
+    return nb_e, o % 8, o // 8
+
+
+def _reorient(face, code):
+    """Partner values in the own face-node layout from the neighbour's face slice (trailing axes
+    (b', a'))."""
+    N = face.shape[-1]
+    b, a = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    x, y = (b, a) if code & 1 else (a, b)
+    ap = N - 1 - x if code & 2 else x
+    bp = N - 1 - y if code & 4 else y
+    return face[..., bp, ap]
+
+
+def _nbr_face(arr_of_dir, nb_e, fp, code, f, p, signed=False):
+    """Face-node values of the neighbours ``nb_e`` (all >= 0) across face f, in the own layout.
+    ``arr_of_dir(l')`` gives the element array to take the neighbour's face l' from; ``signed``
+    multiplies by -s s' (metric rows and contravariant fluxes of direction l')."""
+    s = 1.0 if f & 1 else -1.0
+    out = None
+    for fv, cv in sorted(set(zip(fp.tolist(), code.tolist()))):
+        sel = (fp == fv) & (code == cv)
+        lp, sp = fv >> 1, (1.0 if fv & 1 else -1.0)
+        src = arr_of_dir(lp)
+        v = _reorient(_take(src[..., nb_e[sel], :, :, :], p if fv & 1 else 0, lp), cv)
+        if signed:
+            v = (-s * sp) * v
+        if out is None:
+            out = np.zeros(src.shape[:-4] + (len(nb_e),) + v.shape[-2:], dtype=v.dtype)
+        out[..., sel, :, :] = v
     return out
+
+
+def _partner(arr_of_dir, nbr, orient, elems, f, own, l, own_vals, signed=False):
+    """Face-node values of the partner across face f (direction l) for the elements ``elems``: the
+    neighbour's matching face node, or, on boundary faces, ``own_vals`` (the own face node's)."""
+    nb_e, fp, code = _face_links(nbr, orient, elems, f)
+    out = own_vals.copy()
+    inn = nb_e >= 0
+    if inn.any():
+        out[..., inn, :, :] = _nbr_face(arr_of_dir, nb_e[inn], fp[inn], code[inn], f,
+                                        own_vals.shape[-1] - 1, signed)
+    return out
+
+
+def _metric_rows(metric_all):
+    return lambda lp: metric_all[3 * lp:3 * lp + 3]
 
 
 def _slip_ghost(q, A):
@@ -141,15 +190,15 @@ def _noslip_ghost(q):
     return g
 
 
-def _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas):
+def _partner_state(q_all, metric_all, nbr, orient, elems, f, own, l, bc, gas):
     """Partner state across face f (direction l) for the elements ``elems``: the neighbour's node,
     or the ghost state of the boundary kind the neighbour index names."""
     nb_e = nbr[elems, f]
     bnd = nb_e < 0
-    qn = _take(q_all[:, np.where(bnd, elems, nb_e)], nb, l)
+    qi = _take(q_all[:, elems], own, l)
+    qn = _partner(lambda lp: q_all, nbr, orient, elems, f, own, l, qi)
     if not bnd.any():
         return qn
-    qi = _take(q_all[:, elems], own, l)
     Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
     for code in np.unique(nb_e[bnd]):
         sel = nb_e == code
@@ -168,7 +217,18 @@ def _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas):
     return qn
 
 
-def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
+def _partner_metric(metric_all, nbr, orient, elems, f, own, l):
+    """Partner metric row of direction l (the neighbour's row l', signed; own row on boundaries)."""
+    Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
+    return Ai, _partner(_metric_rows(metric_all), nbr, orient, elems, f, own, l, Ai, signed=True)
+
+
+def _partner_jac(jac_all, nbr, orient, elems, f, own, l):
+    Ji = _take(jac_all[elems], own, l)
+    return Ji, _partner(lambda lp: jac_all, nbr, orient, elems, f, own, l, Ji)
+
+
+def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None, orient=None):
     """Interface SAT and local Lax-Friedrichs dissipation for the elements ``elems``; ``bc`` is
     the state prescribed on Dirichlet boundary faces."""
     flux = G.TWO_POINT[prm.two_point]
@@ -178,9 +238,8 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     w_end = sbp.w[0]
     for l, s, f, own, nb in _faces(sbp.p):
         qi = _take(q, own, l)
-        qn = _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas)
-        Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
-        An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
+        qn = _partner_state(q_all, metric_all, nbr, orient, elems, f, own, l, bc, gas)
+        Ai, An = _partner_metric(metric_all, nbr, orient, elems, f, own, l)
         nbar = 0.5 * (Ai + An)
         sat = -(s / w_end) * (G.contract(flux(qi, qn, gas), nbar) - G.contract(G.euler_flux(qi, gas), Ai))
         if prm.iface_diss == 2:
@@ -201,7 +260,7 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     return out
 
 
-def gradient_theta(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
+def gradient_theta(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None, orient=None):
     """theta_a = D_a w + SAT^theta for the elements ``elems``, shape (3, 5, n, N, N, N)."""
     gas = prm.gas
     w = G.entropy_variables(q_all[:, elems], gas)
@@ -209,15 +268,16 @@ def gradient_theta(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None):
     w_end = sbp.w[0]
     for a, s, f, own, nb in _faces(sbp.p):
         wi = _take(w, own, a)
-        wn = G.entropy_variables(_partner_state(q_all, metric_all, nbr, elems, f, own, nb, a, bc, gas), gas)
+        wn = G.entropy_variables(_partner_state(q_all, metric_all, nbr, orient, elems, f, own, a, bc, gas), gas)
         th[a][_index(w.ndim, own, a)] += (s / (2.0 * w_end)) * (wn - wi)
     return th
 
 
-def contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None):
+def contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None,
+                               orient=None):
     """fhat_l = sum_m A_lm F^V_m with F^V_m = sum_j C_mj g_j and g_j = sum_a A_aj theta_a / J;
     shape (3, 5, n, N, N, N)."""
-    th = gradient_theta(q_all, metric_all, nbr, elems, sbp, prm, bc)
+    th = gradient_theta(q_all, metric_all, nbr, elems, sbp, prm, bc, orient)
     A = metric_all[:, elems]
     J = jac_all[elems]
     g = np.stack([sum(A[3 * a + j] * th[a] for a in range(3)) / J for j in range(3)])
@@ -231,14 +291,14 @@ def chat_ll(q, A_l, J, gas):
     return sum(A_l[m] * C[m, j] * A_l[j] for m in range(3) for j in range(3)) / J
 
 
-def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None):
+def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=None, orient=None):
     """sum_l D_l fhat_l + SAT^V + IP for the elements ``elems`` (eq. NSL, eq. MacroForm)."""
     gas = prm.gas
     elems = np.asarray(elems)
     ring = np.unique(np.concatenate([elems, nbr[elems].ravel()]))
     ring = ring[ring >= 0]
     pos = {int(e): i for i, e in enumerate(ring)}
-    fh_ring = contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, ring, sbp, prm, bc)
+    fh_ring = contravariant_viscous_flux(q_all, metric_all, jac_all, nbr, ring, sbp, prm, bc, orient)
     own_pos = np.array([pos[int(e)] for e in elems])
     fh = fh_ring[:, :, own_pos]
     out = sum(apply_D(sbp.D, fh[l], l) for l in range(3))
@@ -246,23 +306,24 @@ def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=No
     q = q_all[:, elems]
     w = G.entropy_variables(q, gas)
     for l, s, f, own, nb in _faces(sbp.p):
-        nb_e = nbr[elems, f]
+        nb_e, fp, code = _face_links(nbr, orient, elems, f)
         bnd = nb_e < 0
-        nb_pos = np.array([pos[int(e)] if e >= 0 else own_pos[i] for i, e in enumerate(nb_e)])
         fi = _take(fh[l], own, l)
-        fn = _take(fh_ring[l][:, nb_pos], nb, l)
+        fn = fi.copy()
+        if (~bnd).any():
+            ring_nb = np.array([pos[int(e)] for e in nb_e[~bnd]])
+            fn[:, ~bnd] = _nbr_face(lambda lp: fh_ring[lp], ring_nb, fp[~bnd], code[~bnd], f, sbp.p,
+                                    signed=True)
         sat_v = (s / (2.0 * w_end)) * (fn - fi)
         sat_v[:, bnd] = 0.0   # Dirichlet: the boundary viscous flux is the own one
         wall = nb_e == NOSLIP_WALL
         sat_v[4, wall] = -(s / w_end) * fi[4, wall]   # adiabatic wall: zero energy flux
         # interior penalty
         qi = _take(q, own, l)
-        qn = _partner_state(q_all, metric_all, nbr, elems, f, own, nb, l, bc, gas)
+        qn = _partner_state(q_all, metric_all, nbr, orient, elems, f, own, l, bc, gas)
         wi, wn = _take(w, own, l), G.entropy_variables(qn, gas)
-        Ai = _take(metric_all[3 * l:3 * l + 3, elems], own, l)
-        An = _partner(metric_all[3 * l:3 * l + 3], nbr, elems, f, own, nb, l, metric_all[3 * l:3 * l + 3])
-        Ji = _take(jac_all[elems], own, l)
-        Jn = _partner(jac_all, nbr, elems, f, own, nb, l, jac_all)
+        Ai, An = _partner_metric(metric_all, nbr, orient, elems, f, own, l)
+        Ji, Jn = _partner_jac(jac_all, nbr, orient, elems, f, own, l)
         Lm = 0.5 * (chat_ll(qi, Ai, Ji, gas) + chat_ll(qn, An, Jn, gas))
         ip = -(prm.eta / w_end) * np.einsum("ab...,b...->a...", Lm, wi - wn)
         out[_index(out.ndim, own, l)] += sat_v + ip
@@ -270,13 +331,14 @@ def viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm: Params, bc=No
 
 
 def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chunk=None, bc=None,
-             source=None):
+             source=None, orient=None):
     """dq/dt for the elements ``elems`` (all by default), shape (5, n, N, N, N).
 
     ``chunk`` splits the element list into groups evaluated one after another (memory only).
     ``bc`` (shape of q) holds the state read at the face nodes of Dirichlet boundary faces
     (neighbour index -1; walls, -2 and -3, need no data); ``source`` (shape of q) is added to
-    dq/dt.
+    dq/dt; ``orient`` ([K, 6], f' + 8 code) gives the neighbour face and orientation of every
+    interior face (None: aligned faces).
     """
     K = q_all.shape[1]
     if elems is None:
@@ -284,13 +346,13 @@ def residual(q_all, metric_all, jac_all, nbr, sbp, prm: Params, elems=None, chun
     elems = np.asarray(elems)
     if chunk is not None and len(elems) > chunk:
         return np.concatenate([residual(q_all, metric_all, jac_all, nbr, sbp, prm,
-                                        elems[i:i + chunk], bc=bc, source=source)
+                                        elems[i:i + chunk], bc=bc, source=source, orient=orient)
                                for i in range(0, len(elems), chunk)], axis=1)
     q = q_all[:, elems]
     rhs = -volume_term(q, metric_all[:, elems], sbp, prm)
-    rhs = rhs + inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm, bc)
+    rhs = rhs + inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm, bc, orient)
     if prm.gas.mu != 0.0:
-        rhs = rhs + viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm, bc)
+        rhs = rhs + viscous_term(q_all, metric_all, jac_all, nbr, elems, sbp, prm, bc, orient)
     out = rhs / jac_all[elems]
     if source is not None:
         out = out + source[:, elems]
