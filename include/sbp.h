@@ -81,6 +81,17 @@ typedef struct sbp_problem {
      * source: forcing added to dq/dt (e.g. of a manufactured solution). */
     const double *bc_state;
     const double *source;
+    /* Optional device [K][6] int32 (NULL = aligned faces): face orientation of unstructured
+     * meshes.  For an interior face f of element e, face_orient[e*6 + f] = f' + 8*code: the
+     * neighbour's face f' = 2*l' + s' (any of its six) and the orientation code (0..7) of its
+     * face-node grid on the own one.  With the own face node's tangential indices (a, b) (the two
+     * indices other than i_l, in increasing direction order), the partner node has tangential
+     * indices (a', b') = (F_a(x), F_b(y)), (x, y) = (b, a) if bit 0 of code is set, else (a, b),
+     * F_a(x) = N-1-x if bit 1 is set (else x), F_b(y) = N-1-y if bit 2 is set (else y).  The
+     * partner's metric row and contravariant viscous flux are those of its direction l', times
+     * -1 when s' == s.  Entries of boundary faces are not read; an entry outside that range on an
+     * interior face is a mesh error (sticky flag).  NULL means f' = f ^ 1 and code 0. */
+    const int32_t *face_orient;
 } sbp_problem;
 
 /* Boundary kinds, written into nbr in place of a neighbour index.  A boundary face node's partner
@@ -147,7 +158,7 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
  * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0) on periodic problems
  * (bc_state == NULL) with iface_diss 0 or 1; other fluxes, boundary data or matrix dissipation give
- * SBP_ERR_ARG; a boundary face in nbr (any negative entry) raises the mesh flag (SBP_ERR_MESH
+ * SBP_ERR_ARG, as does a face_orient table; a boundary face in nbr (any negative entry) raises the mesh flag (SBP_ERR_MESH
  * from sbp_status()) and its terms are left out; degrees above SBP_MAX_VJP_P
  * give SBP_ERR_DEGREE.  A source term does not enter the product.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
  * in the interface dissipation takes the own side on ties. */

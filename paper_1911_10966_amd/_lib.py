@@ -42,6 +42,7 @@ class sbp_problem(ctypes.Structure):
         ("reserved", ctypes.c_int32),
         ("bc_state", ctypes.c_void_p),
         ("source", ctypes.c_void_p),
+        ("face_orient", ctypes.c_void_p),
     ]
 
 

@@ -62,8 +62,9 @@ def metrics(p: int, coords: torch.Tensor):
 
 @dataclass
 class Problem:
-    """One problem on the device: degree, element count, neighbour table, metrics, constants, and
-    optionally Dirichlet boundary data and a source term."""
+    """One problem on the device: degree, element count, neighbour table (negative entries are
+    boundary kinds), metrics, constants, and optionally Dirichlet boundary data, a source term and
+    the face-orientation table of an unstructured mesh."""
 
     p: int
     n_elem: int
@@ -79,6 +80,7 @@ class Problem:
     two_point: int = 0
     bc_state: Optional[torch.Tensor] = None   # float64 (5, nodes): Dirichlet state, faces with nbr -1
     source: Optional[torch.Tensor] = None     # float64 (5, nodes): added to dq/dt
+    face_orient: Optional[torch.Tensor] = None  # int32 (K, 6): f' + 8 code per face; None aligned
 
     @property
     def nodes(self) -> int:
@@ -96,6 +98,11 @@ class Problem:
                 if t.numel() != 5 * self.nodes:
                     raise ValueError(f"{name} has {t.numel()} entries, expected {5 * self.nodes}")
             extra.append(None if t is None else t.data_ptr())
+        if self.face_orient is not None:
+            _need(self.face_orient, torch.int32, "face_orient")
+            if self.face_orient.numel() != 6 * self.n_elem:
+                raise ValueError(f"face_orient has {self.face_orient.numel()} entries, expected {6 * self.n_elem}")
+        extra.append(None if self.face_orient is None else self.face_orient.data_ptr())
         return _lib.sbp_problem(self.p, self.iface_diss, self.n_elem, self.nbr.data_ptr(),
                                 self.metric.data_ptr(), self.jac.data_ptr(), self.gamma, self.R,
                                 self.mu, self.Pr, self.eta, self.two_point, 0, *extra)

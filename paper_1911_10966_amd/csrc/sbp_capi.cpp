@@ -138,6 +138,7 @@ int check_problem(const sbp_problem &pr) {
     if (pr.mu > 0.0 && !(pr.Pr > 0.0)) return SBP_ERR_ARG;
     if (pr.two_point < 0 || pr.two_point > 3 || pr.reserved != 0) return SBP_ERR_ARG;
     if ((pr.bc_state && !aligned8(pr.bc_state)) || (pr.source && !aligned8(pr.source))) return SBP_ERR_ARG;
+    if (pr.face_orient && (reinterpret_cast<uintptr_t>(pr.face_orient) & 3u) != 0) return SBP_ERR_ARG;
     if (pr.iface_diss < 0 || pr.iface_diss > 2) return SBP_ERR_ARG;
     if (pr.iface_diss == 2 && pr.two_point != SBP_FLUX_CHANDRASHEKAR &&
         pr.two_point != SBP_FLUX_KENNEDY_GRUBER)
@@ -284,6 +285,7 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
             d.thb = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.thb[b]) : nullptr;
             d.bc = pr.bc_state;
             d.src = pr.source;
+            d.orient = pr.face_orient;
             d.K = pr.n_elem;
             d.nodes = nodes_of(pr);
             d.off = off[b];
@@ -527,7 +529,7 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
         return SBP_ERR_ARG;
     for (int b = 0; b < n_prob; ++b) {
         if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].bc_state != nullptr ||
-            probs[b].iface_diss == 2)
+            probs[b].iface_diss == 2 || probs[b].face_orient != nullptr)
             return SBP_ERR_ARG;
         if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
     }

@@ -230,6 +230,7 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
     a.aux = P.thb;
     a.bc = P.bc;
     a.src = P.src;
+    a.orient = P.orient;
     a.status = g.status;
     a.D = g.D;
     a.K = P.K;
@@ -342,19 +343,57 @@ __device__ __forceinline__ int face_kind(const ResArgs &a, long long nb) {
     return nb == -3 ? FACE_WALL : FACE_INVALID;
 }
 
-// Partner of a face node: node pg of the neighbour or, on a boundary face, a ghost at the own node
-// pg with the own metrics and J carrying the prescribed state (Dirichlet), the own state with the
-// momentum reflected about the face (slip wall), or the own state with the momentum reversed
-// (no-slip wall: zero velocity and the own temperature on average).
+// Where the partner of a face node lies on the neighbour across face f = 2 l + side of element e:
+// the neighbour's face fp, the partner's local node index lno and tangential index tp on face fp,
+// and the sign sg (-s s') that turns the neighbour's direction l' = fp / 2 into the own direction
+// l.  (ta, tb) are the own face node's tangential indices.  Without an orientation table faces are
+// aligned: fp = f ^ 1, the same tangential indices, sg = 1.  An invalid table entry gives ok =
+// false and the aligned partner (so that every index stays inside the neighbour element).
+struct FaceLink {
+    int fp, lno, tp;
+    double sg;
+    bool ok;
+};
+
+template <int N>
+__device__ __forceinline__ FaceLink face_link(const ResArgs &a, long long e, int f, int ta, int tb) {
+    FaceLink r;
+    int code = 0;
+    r.fp = f ^ 1;
+    r.ok = true;
+    if (a.orient != nullptr) {
+        const int o = a.orient[e * 6 + f];
+        if (o >= 0 && o < 64 && (o & 7) < 6) {
+            r.fp = o & 7;
+            code = o >> 3;
+        } else {
+            r.ok = false;
+        }
+    }
+    const int x = (code & 1) ? tb : ta, y = (code & 1) ? ta : tb;
+    const int ap = (code & 2) ? N - 1 - x : x, bp = (code & 4) ? N - 1 - y : y;
+    const int lp = r.fp >> 1, ilp = (r.fp & 1) ? N - 1 : 0;
+    r.lno = lp == 0 ? ilp + N * ap + N * N * bp
+                    : (lp == 1 ? ap + N * ilp + N * N * bp : ap + N * bp + N * N * ilp);
+    r.tp = ap + N * bp;
+    r.sg = ((r.fp & 1) == (f & 1)) ? -1.0 : 1.0;
+    return r;
+}
+
+// Partner of a face node: node pg of the neighbour (metric row of its direction l, times sg) or,
+// on a boundary face, a ghost at the own node pg with the own metrics (l the own direction, sg = 1)
+// and J carrying the prescribed state (Dirichlet), the own state with the momentum reflected
+// about the face (slip wall), or the own state with the momentum reversed (no-slip wall: zero
+// velocity and the own temperature on average).
 template <bool VISC>
 __device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, int kind, int l,
-                                              FaceNbr &n) {
+                                              double sg, FaceNbr &n) {
     const long long nodes = a.nodes;
     const double *qs = kind == FACE_DIRICHLET ? a.bc : a.q;
 #pragma unroll
     for (int c = 0; c < 5; ++c) n.q[c] = qs[c * nodes + pg];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) n.A[m] = a.metric[(3 * l + m) * nodes + pg];
+    for (int m = 0; m < 3; ++m) n.A[m] = sg * a.metric[(3 * l + m) * nodes + pg];
     n.J = (VISC && a.eta != 0.0) ? a.jac[pg] : 1.0;
     if (kind == FACE_SLIP) {
         const double mn = (n.q[1] * n.A[0] + n.q[2] * n.A[1] + n.q[3] * n.A[2]) *
@@ -455,9 +494,10 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
 
 template <int FLUX, bool VISC, bool MD = false>
 __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, const double Ai[3],
-                                           long long pg, int kind, int l, double s, double v[9]) {
+                                           long long pg, int kind, int l, double sg, double s,
+                                           double v[9]) {
     FaceNbr nb;
-    load_face_nbr<VISC>(a, pg, kind, l, nb);
+    load_face_nbr<VISC>(a, pg, kind, l, sg, nb);
     face_terms<FLUX, VISC, MD>(a, ow, Ai, nb, s, v);
 }
 

@@ -20,6 +20,7 @@ struct ResArgs {
     double *aux;           // viscous per-node scratch of the plane kernels, [16][nodes] (mu > 0 only)
     const double *bc;      // Dirichlet state of boundary faces (nbr == -1), SoA [5][nodes], or null
     const double *src;     // source added to dq/dt, SoA [5][nodes], or null
+    const int32_t *orient; // face orientation [K][6] (f' + 8 code), or null (aligned faces)
     int *status;           // sticky flags
     const double *D;       // [N*N] collocation derivative
     long long K;
@@ -42,6 +43,7 @@ struct ProbDev {
     double *thb;
     const double *bc;
     const double *src;
+    const int32_t *orient;
     long long K;
     long long nodes;
     long long off;

@@ -222,10 +222,18 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int ta = t % N, tb = t / N;
                 const int lno = l == 0 ? il + N * ta + N2 * tb
                                        : (l == 1 ? ta + N * il + N2 * tb : ta + N * tb + N2 * il);
-                const int sl = l == 0 ? 1 : (l == 1 ? N : N2);
                 const int pl = es * N3 + lno;
                 const long long go = ee * N3 + lno;
-                const long long pg = kind == FACE_INTERIOR ? nb * N3 + lno + (N - 1 - 2 * il) * sl : go;
+                long long pg = go;
+                int lp = l;
+                double sg = 1.0;
+                if (kind == FACE_INTERIOR) {
+                    const FaceLink k = face_link<N>(a, ee, f, ta, tb);
+                    if (!k.ok) atomicOr(a.status, FLAG_MESH);
+                    pg = nb * N3 + k.lno;
+                    lp = k.fp >> 1;
+                    sg = k.sg;
+                }
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -243,8 +251,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 else mi.k = s_buf[F_K * NODES + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, l,
-                                       side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, lp, sg,
+                                           side ? 1.0 : -1.0, v);
             }
 #pragma unroll
             for (int c = 0; c < NV; ++c) fsl[c * FACE_ITEMS + it] = v[c];
@@ -288,9 +296,19 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 if (kind == FACE_INTERIOR) faces |= 1 << l;
                 if (kind == FACE_WALL) wfaces |= 1 << l;
                 sfaces |= 1 << l;
-                const long long pg = kind == FACE_INTERIOR ? nb * N3 + ln + (N - 1 - 2 * il) * stride[l] : g;
+                long long pg = g;
+                int lp = l;
+                double sg = 1.0;
+                if (kind == FACE_INTERIOR) {
+                    const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
+                    const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb);
+                    if (!k.ok) atomicOr(a.status, FLAG_MESH);
+                    pg = nb * N3 + k.lno;
+                    lp = k.fp >> 1;
+                    sg = k.sg;
+                }
                 double v[9];
-                face_terms<FLUX, VISC, MD>(a, own, A[l], pg, kind, l, side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC, MD>(a, own, A[l], pg, kind, lp, sg, side ? 1.0 : -1.0, v);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {
@@ -456,9 +474,10 @@ __device__ __forceinline__ bool visc_fixup_add(const ResArgs &a, long long gl, d
         const double s = side ? 1.0 : -1.0;
         const long long nb = a.nbr[e * 6 + 2 * l + side];
         if (nb < 0 || nb >= a.K) continue;
-        const int t = tangential_index<N>(l, i1, i2, i3);
-        const double *tr = a.trace + ((nb * 6 + 2 * l + (1 - side)) * 4) * N2 + t;
-        const double cf = 0.5 * s / a.w_end;
+        const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
+        const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb);
+        const double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
+        const double cf = 0.5 * s * k.sg / a.w_end;
 #pragma unroll
         for (int c = 0; c < 4; ++c) add[c] = fma(cf, tr[c * N2], add[c]);
         any = true;

@@ -228,7 +228,16 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 const int j1 = l == 0 ? il : t, j2 = l == 0 ? t : il;
                 const int lno = j1 + N * j2 + N2 * j3;
                 const long long go = e * N3 + lno;
-                const long long pg = kind == FACE_INTERIOR ? nb * N3 + lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N) : go;
+                long long pg = go;
+                int lp = l;
+                double sg = 1.0;
+                if (kind == FACE_INTERIOR) {
+                    const FaceLink k = face_link<N>(a, e, f, t, j3);
+                    if (!k.ok) atomicOr(a.status, FLAG_MESH);
+                    pg = nb * N3 + k.lno;
+                    lp = k.fp >> 1;
+                    sg = k.sg;
+                }
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -237,8 +246,8 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + j1 + N * j2);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, l,
-                                       side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, lp, sg,
+                                           side ? 1.0 : -1.0, v);
             }
         }
 #pragma unroll
@@ -361,7 +370,16 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 const int il = side ? N - 1 : 0;
                 const int lno = t + N * j2 + N2 * il;
                 const long long go = ee * N3 + lno;
-                const long long pg = kind == FACE_INTERIOR ? nb * N3 + lno + (N - 1 - 2 * il) * N2 : go;
+                long long pg = go;
+                int lp = 2;
+                double sg = 1.0;
+                if (kind == FACE_INTERIOR) {
+                    const FaceLink k = face_link<N>(a, ee, 4 + side, t, j2);
+                    if (!k.ok) atomicOr(a.status, FLAG_MESH);
+                    pg = nb * N3 + k.lno;
+                    lp = k.fp >> 1;
+                    sg = k.sg;
+                }
                 double qi[5], Ai[3];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
@@ -370,8 +388,8 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 const Node mi = staged_node(s_buf, NODES, ip * N2 + t + N * il);
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
-                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, 2,
-                                       side ? 1.0 : -1.0, v);
+                face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, lp, sg,
+                                           side ? 1.0 : -1.0, v);
             }
         }
 #pragma unroll
@@ -525,7 +543,6 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_c(const GroupArgs 
     line_grad4<N>(s_buf, NODES, 4, s_D, tid, i2, N, acc);
     // SAT^V = (s / (2 w_end)) (fhat_l,nu - fhat_l,i) on every face of the node
     const int idx[3] = {i1, i2, i3};
-    const int lstride[3] = {1, N, N2};
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const int il = idx[l];
@@ -539,16 +556,28 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_c(const GroupArgs 
             continue;
         }
         const double cs = 0.5 * (side ? 1.0 : -1.0) * a.isw;
-        if (l < 2) {
-            const long long pg = nb * N3 + (gn - e * N3) + (N - 1 - 2 * il) * lstride[l];
+        // the neighbour's fhat of its direction l' at the partner node: the per-node scratch
+        // for l' = 0, 1, the xi3 face trace for l' = 2
+        const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
+        const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb);
+        const int lp = k.fp >> 1;
+        double fn[4];
+        if (lp < 2) {
+            const long long pg = nb * N3 + k.lno;
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc[c] = fma(cs, a.aux[(AUX_FH + 4 * l + c) * nodes + pg] - fh[l][c], acc[c]);
+            for (int c = 0; c < 4; ++c) fn[c] = k.sg * a.aux[(AUX_FH + 4 * lp + c) * nodes + pg];
         } else {
-            // own half was added with the xi3 divergence; the neighbour's face trace
-            const double *tr = a.trace + ((nb * 6 + 4 + (1 - side)) * 4) * N2 + i1 + N * i2;
+            const double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c] = fma(cs, tr[c * N2], acc[c]);
+            for (int c = 0; c < 4; ++c) fn[c] = k.sg * tr[c * N2];
+        }
+        if (l < 2) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = fma(cs, fn[c] - fh[l][c], acc[c]);
+        } else {
+            // the own half was added with the xi3 divergence
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = fma(cs, fn[c], acc[c]);
         }
     }
     const double iJ = rcp(a.jac[gn]);
