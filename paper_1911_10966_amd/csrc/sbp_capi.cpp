@@ -208,7 +208,8 @@ struct GroupPlan {
     int p = 0;
     bool visc = false;
     int flux = 0;
-    bool md = false;  // matrix interface dissipation
+    bool md = false;      // matrix interface dissipation
+    bool orient = false;  // face-orientation tables
     std::vector<int> members;
     sbp::ProbDev *d_probs = nullptr;
     long long *d_node_start = nullptr;
@@ -259,9 +260,12 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
     for (int b = 0; b < n; ++b) {
         const bool visc = probs[b].mu > 0.0;
         const bool md = probs[b].iface_diss == 2;
+        const bool orient = probs[b].face_orient != nullptr;
         GroupPlan *gp = nullptr;
         for (auto &g : plan->groups)
-            if (g.p == probs[b].p && g.visc == visc && g.flux == probs[b].two_point && g.md == md) gp = &g;
+            if (g.p == probs[b].p && g.visc == visc && g.flux == probs[b].two_point && g.md == md &&
+                g.orient == orient)
+                gp = &g;
         if (!gp) {
             plan->groups.emplace_back();
             gp = &plan->groups.back();
@@ -269,6 +273,7 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
             gp->visc = visc;
             gp->flux = probs[b].two_point;
             gp->md = md;
+            gp->orient = orient;
         }
         gp->members.push_back(b);
     }
@@ -345,7 +350,7 @@ int residual_group(const GroupPlan &g, const double *q, double *out, char *ws, h
                    bool fixup, int variant) {
     sbp::GroupArgs a = group_args(g, variant, q, out, ws);
     if (a.D == nullptr) return SBP_ERR_HIP;
-    return sbp::launch_group_residual(g.p, g.visc, g.flux, g.md, variant, a, s, fixup) == 0 ? SBP_OK
+    return sbp::launch_group_residual(g.p, g.visc, g.flux, g.md, g.orient, variant, a, s, fixup) == 0 ? SBP_OK
                                                                                            : SBP_ERR_HIP;
 }
 
@@ -600,7 +605,7 @@ int sbp_autotune(const sbp_problem *probs, int32_t n_prob, const double *q, doub
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SBP_ERR_HIP;
     for (auto &g : plan->groups) {
-        const int nv = (g.flux == 0 && !g.md) ? sbp::schedule_count(g.p) : 1;
+        const int nv = (g.flux == 0 && !g.md && !g.orient) ? sbp::schedule_count(g.p) : 1;
         float best = 0.0f;
         int best_v = 0;
         for (int v = 0; v < nv; ++v) {
@@ -645,7 +650,7 @@ int sbp_set_schedule(const sbp_problem *probs, int32_t n_prob, void *ws, size_t 
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (auto &g : plan->groups)
         if (g.p == p) {
-            if ((g.flux != SBP_FLUX_CHANDRASHEKAR || g.md) && variant != 0) return SBP_ERR_ARG;
+            if ((g.flux != SBP_FLUX_CHANDRASHEKAR || g.md || g.orient) && variant != 0) return SBP_ERR_ARG;
             g.variant = variant;
         }
     plan->generation = ++g_generation;

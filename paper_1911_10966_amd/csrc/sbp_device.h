@@ -347,28 +347,36 @@ __device__ __forceinline__ int face_kind(const ResArgs &a, long long nb) {
 // the neighbour's face fp, the partner's local node index lno and tangential index tp on face fp,
 // and the sign sg (-s s') that turns the neighbour's direction l' = fp / 2 into the own direction
 // l.  (ta, tb) are the own face node's tangential indices.  Without an orientation table faces are
-// aligned: fp = f ^ 1, the same tangential indices, sg = 1.  An invalid table entry gives ok =
+// aligned: fp = f ^ 1, the same tangential indices (local index aligned_lno), sg = 1.  An invalid table entry gives ok =
 // false and the aligned partner (so that every index stays inside the neighbour element).
+// ORIENT = false compiles the aligned case only (kernels launched for problems without a table).
 struct FaceLink {
     int fp, lno, tp;
     double sg;
     bool ok;
 };
 
-template <int N>
-__device__ __forceinline__ FaceLink face_link(const ResArgs &a, long long e, int f, int ta, int tb) {
+template <int N, bool ORIENT = true>
+__device__ __forceinline__ FaceLink face_link(const ResArgs &a, long long e, int f, int ta, int tb,
+                                              int aligned_lno) {
     FaceLink r;
+    r.ok = true;
+    if (!ORIENT || a.orient == nullptr) {
+        // aligned faces: the caller's mirrored node index
+        r.fp = f ^ 1;
+        r.lno = aligned_lno;
+        r.tp = ta + N * tb;
+        r.sg = 1.0;
+        return r;
+    }
     int code = 0;
     r.fp = f ^ 1;
-    r.ok = true;
-    if (a.orient != nullptr) {
-        const int o = a.orient[e * 6 + f];
-        if (o >= 0 && o < 64 && (o & 7) < 6) {
-            r.fp = o & 7;
-            code = o >> 3;
-        } else {
-            r.ok = false;
-        }
+    const int o = a.orient[e * 6 + f];
+    if (o >= 0 && o < 64 && (o & 7) < 6) {
+        r.fp = o & 7;
+        code = o >> 3;
+    } else {
+        r.ok = false;
     }
     const int x = (code & 1) ? tb : ta, y = (code & 1) ? ta : tb;
     const int ap = (code & 2) ? N - 1 - x : x, bp = (code & 4) ? N - 1 - y : y;

@@ -90,8 +90,9 @@ struct Schedule {
 int schedule_count(int p);
 Schedule schedule_of(int p, int variant);
 // md: matrix interface dissipation (iface_diss = 2; default schedule, fluxes 0 and 2 only).
-int launch_group_residual(int p, bool visc, int flux, bool md, int variant, const GroupArgs &g,
-                          hipStream_t s, bool fixup);
+// orient: the group's problems carry face-orientation tables (default schedule).
+int launch_group_residual(int p, bool visc, int flux, bool md, bool orient, int variant,
+                          const GroupArgs &g, hipStream_t s, bool fixup);
 int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArgs &r, hipStream_t s);
 // Degrees whose elements exceed one workgroup (p >= 9) run as passes over node planes; a
 // schedule's `epw` is then the number of planes per workgroup.

@@ -23,8 +23,9 @@ constexpr int tile_fields(bool visc) { return visc ? 24 : 20; }
 constexpr int kFaceItemsFrom = 6;
 
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
-// MD: matrix interface dissipation (iface_diss = 2) instead of Lax-Friedrichs.
-template <int N, int EPW, bool VISC, int FLUX, bool MD>
+// MD: matrix interface dissipation (iface_diss = 2) instead of Lax-Friedrichs.  OR: the problem has
+// a face-orientation table (unstructured faces); without it the aligned partners are compiled in.
+template <int N, int EPW, bool VISC, int FLUX, bool MD, bool OR>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
                                               const double *s_D) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
@@ -228,7 +229,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 int lp = l;
                 double sg = 1.0;
                 if (kind == FACE_INTERIOR) {
-                    const FaceLink k = face_link<N>(a, ee, f, ta, tb);
+                    const FaceLink k = face_link<N, OR>(a, ee, f, ta, tb,
+                                                    lno + (N - 1 - 2 * il) * (l == 0 ? 1 : (l == 1 ? N : N2)));
                     if (!k.ok) atomicOr(a.status, FLAG_MESH);
                     pg = nb * N3 + k.lno;
                     lp = k.fp >> 1;
@@ -301,7 +303,8 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 double sg = 1.0;
                 if (kind == FACE_INTERIOR) {
                     const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
-                    const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb);
+                    const FaceLink k = face_link<N, OR>(a, e, 2 * l + side, ta, tb,
+                                                    ln + (N - 1 - 2 * il) * stride[l]);
                     if (!k.ok) atomicOr(a.status, FLAG_MESH);
                     pg = nb * N3 + k.lno;
                     lp = k.fp >> 1;
@@ -431,7 +434,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
 // Residual over a group of problems.  Non-persistent: one block per element tile.  Persistent:
 // a grid sized to the resident capacity walks the tiles (the grid is a multiple of the XCD count,
 // so the XCD-contiguous remap of tile indices still holds).
-template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE, bool MD>
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE, bool MD, bool OR>
 __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
 __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
 k_residual(const GroupArgs g) {
@@ -443,13 +446,13 @@ k_residual(const GroupArgs g) {
         const long long vb = xcd_block(blockIdx.x, gridDim.x);
         const int b = find_problem(g.block_start, g.n, vb);
         const ResArgs a = problem_view(g, g.probs[b], g.out);
-        residual_tile<N, EPW, VISC, FLUX, MD>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+        residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
     } else {
         for (long long it = blockIdx.x; it < g.total_blocks; it += gridDim.x) {
             const long long vb = xcd_block(it, g.total_blocks);
             const int b = find_problem(g.block_start, g.n, vb);
             const ResArgs a = problem_view(g, g.probs[b], g.out);
-            residual_tile<N, EPW, VISC, FLUX, MD>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+            residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
             __syncthreads();
         }
     }
@@ -475,7 +478,8 @@ __device__ __forceinline__ bool visc_fixup_add(const ResArgs &a, long long gl, d
         const long long nb = a.nbr[e * 6 + 2 * l + side];
         if (nb < 0 || nb >= a.K) continue;
         const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
-        const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb);
+        const int strd = l == 0 ? 1 : (l == 1 ? N : N2);
+        const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * strd);
         const double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
         const double cf = 0.5 * s * k.sg / a.w_end;
 #pragma unroll
@@ -627,10 +631,11 @@ int device_cus() {
     return cus;
 }
 
-template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE = 0, bool MD = false>
+template <int N, int EPW, bool VISC, int FLUX, bool PERSIST, int WPE = 0, bool MD = false,
+          bool OR = false>
 int launch_res_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
-    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST, WPE, MD>;
+    auto kern = k_residual<N, EPW, VISC, FLUX, PERSIST, WPE, MD, OR>;
     long long grid = g.total_blocks;
     if (PERSIST) {
         static int per_cu = 0;
@@ -675,6 +680,31 @@ int launch_res_md(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
                             : launch_res_k<N, EPW, false, 0, false, 0, true>(g, s);
         case 2: return visc ? launch_res_k<N, EPW, true, 2, false, 0, true>(g, s)
                             : launch_res_k<N, EPW, false, 2, false, 0, true>(g, s);
+        default: return -1;
+    }
+}
+
+// Problems with a face-orientation table: default schedule, every flux and dissipation.
+template <int N, int EPW>
+int launch_res_or(bool visc, int flux, bool md, const GroupArgs &g, hipStream_t s) {
+    if (md) {
+        switch (flux) {
+            case 0: return visc ? launch_res_k<N, EPW, true, 0, false, 0, true, true>(g, s)
+                                : launch_res_k<N, EPW, false, 0, false, 0, true, true>(g, s);
+            case 2: return visc ? launch_res_k<N, EPW, true, 2, false, 0, true, true>(g, s)
+                                : launch_res_k<N, EPW, false, 2, false, 0, true, true>(g, s);
+            default: return -1;
+        }
+    }
+    switch (flux) {
+        case 0: return visc ? launch_res_k<N, EPW, true, 0, false, 0, false, true>(g, s)
+                            : launch_res_k<N, EPW, false, 0, false, 0, false, true>(g, s);
+        case 1: return visc ? launch_res_k<N, EPW, true, 1, false, 0, false, true>(g, s)
+                            : launch_res_k<N, EPW, false, 1, false, 0, false, true>(g, s);
+        case 2: return visc ? launch_res_k<N, EPW, true, 2, false, 0, false, true>(g, s)
+                            : launch_res_k<N, EPW, false, 2, false, 0, false, true>(g, s);
+        case 3: return visc ? launch_res_k<N, EPW, true, 3, false, 0, false, true>(g, s)
+                            : launch_res_k<N, EPW, false, 3, false, 0, false, true>(g, s);
         default: return -1;
     }
 }
@@ -725,16 +755,28 @@ Schedule schedule_of(int p, int v) {
     }
 }
 
-int launch_group_residual(int p, bool visc, int flux, bool md, int variant, const GroupArgs &g,
-                          hipStream_t s, bool fixup) {
+int launch_group_residual(int p, bool visc, int flux, bool md, bool orient, int variant,
+                          const GroupArgs &g, hipStream_t s, bool fixup) {
     if (variant < 0 || variant >= schedule_count(p)) return -1;
-    if ((flux != 0 || md) && variant != 0) return -1;
+    if ((flux != 0 || md || orient) && variant != 0) return -1;
     const Schedule sc = schedule_of(p, variant);
     // high degrees: plane passes, which finish SAT^V themselves (no fixup)
     if (p >= kFirstPlaneP) return launch_group_residual_planes(p, sc.epw, visc, flux, md, g, s);
     int rc = -1;
     const bool P1 = sc.persistent != 0;
-    if (md) {
+    if (orient) {
+        switch (p) {
+            case 1: rc = launch_res_or<2, 8>(visc, flux, md, g, s); break;
+            case 2: rc = launch_res_or<3, 2>(visc, flux, md, g, s); break;
+            case 3: rc = launch_res_or<4, 1>(visc, flux, md, g, s); break;
+            case 4: rc = launch_res_or<5, 1>(visc, flux, md, g, s); break;
+            case 5: rc = launch_res_or<6, 1>(visc, flux, md, g, s); break;
+            case 6: rc = launch_res_or<7, 1>(visc, flux, md, g, s); break;
+            case 7: rc = launch_res_or<8, 1>(visc, flux, md, g, s); break;
+            case 8: rc = launch_res_or<9, 1>(visc, flux, md, g, s); break;
+            default: return -1;
+        }
+    } else if (md) {
         switch (p) {
             case 1: rc = launch_res_md<2, 8>(visc, flux, g, s); break;
             case 2: rc = launch_res_md<3, 2>(visc, flux, g, s); break;

@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 int lp = l;
                 double sg = 1.0;
                 if (kind == FACE_INTERIOR) {
-                    const FaceLink k = face_link<N>(a, e, f, t, j3);
+                    const FaceLink k = face_link<N>(a, e, f, t, j3, lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N));
                     if (!k.ok) atomicOr(a.status, FLAG_MESH);
                     pg = nb * N3 + k.lno;
                     lp = k.fp >> 1;
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 int lp = 2;
                 double sg = 1.0;
                 if (kind == FACE_INTERIOR) {
-                    const FaceLink k = face_link<N>(a, ee, 4 + side, t, j2);
+                    const FaceLink k = face_link<N>(a, ee, 4 + side, t, j2, lno + (N - 1 - 2 * il) * N2);
                     if (!k.ok) atomicOr(a.status, FLAG_MESH);
                     pg = nb * N3 + k.lno;
                     lp = k.fp >> 1;
@@ -559,7 +559,9 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_c(const GroupArgs 
         // the neighbour's fhat of its direction l' at the partner node: the per-node scratch
         // for l' = 0, 1, the xi3 face trace for l' = 2
         const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
-        const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb);
+        const int lne = (int)(gn - e * N3);  // element-local node index
+        const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb,
+                                        lne + (N - 1 - 2 * il) * (l == 0 ? 1 : (l == 1 ? N : N2)));
         const int lp = k.fp >> 1;
         double fn[4];
         if (lp < 2) {
