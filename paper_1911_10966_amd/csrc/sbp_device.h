@@ -221,16 +221,16 @@ __device__ __forceinline__ int find_problem(const long long *start, int n, long 
 
 __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDev &P, double *out) {
     ResArgs a;
-    a.q = g.q + P.off;
-    a.out = out + P.off;
-    a.metric = P.metric;
-    a.jac = P.jac;
-    a.nbr = P.nbr;
-    a.trace = P.trace;
-    a.aux = P.thb;
-    a.bc = P.bc;
-    a.src = P.src;
-    a.orient = P.orient;
+    a.q = (const SBP_GLOBAL double *)(g.q + P.off);
+    a.out = (SBP_GLOBAL double *)(out + P.off);
+    a.metric = (const SBP_GLOBAL double *)P.metric;
+    a.jac = (const SBP_GLOBAL double *)P.jac;
+    a.nbr = (const SBP_GLOBAL int32_t *)P.nbr;
+    a.trace = (SBP_GLOBAL double *)P.trace;
+    a.aux = (SBP_GLOBAL double *)P.thb;
+    a.bc = (const SBP_GLOBAL double *)P.bc;
+    a.src = (const SBP_GLOBAL double *)P.src;
+    a.orient = (const SBP_GLOBAL int32_t *)P.orient;
     a.status = g.status;
     a.D = g.D;
     a.K = P.K;
@@ -397,7 +397,7 @@ template <bool VISC>
 __device__ __forceinline__ void load_face_nbr(const ResArgs &a, long long pg, int kind, int l,
                                               double sg, FaceNbr &n) {
     const long long nodes = a.nodes;
-    const double *qs = kind == FACE_DIRICHLET ? a.bc : a.q;
+    const SBP_GLOBAL double *qs = kind == FACE_DIRICHLET ? a.bc : a.q;
 #pragma unroll
     for (int c = 0; c < 5; ++c) n.q[c] = qs[c * nodes + pg];
 #pragma unroll

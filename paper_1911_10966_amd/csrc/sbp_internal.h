@@ -9,19 +9,28 @@ namespace sbp {
 
 enum : int { FLAG_NONPHYSICAL = 1, FLAG_MESH = 2 };
 
+// Device code reaches the problem arrays through pointers read from memory (the group's problem
+// table), whose address space the compiler cannot infer; without this qualifier every access
+// becomes a flat instruction, which also counts against the LDS wait counter.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SBP_GLOBAL __attribute__((address_space(1)))
+#else
+#define SBP_GLOBAL
+#endif
+
 // Everything a residual launch for one problem needs.  Arrays are device pointers.
 struct ResArgs {
-    const double *q;       // SoA [5][nodes]
-    double *out;           // SoA [5][nodes]
-    const double *metric;  // SoA [9][nodes]
-    const double *jac;     // [nodes]
-    const int32_t *nbr;    // [K][6]
-    double *trace;         // viscous face traces [K][6][4][N^2] (mu > 0 only)
-    double *aux;           // viscous per-node scratch of the plane kernels, [16][nodes] (mu > 0 only)
-    const double *bc;      // Dirichlet state of boundary faces (nbr == -1), SoA [5][nodes], or null
-    const double *src;     // source added to dq/dt, SoA [5][nodes], or null
-    const int32_t *orient; // face orientation [K][6] (f' + 8 code), or null (aligned faces)
-    int *status;           // sticky flags
+    const SBP_GLOBAL double *q;       // SoA [5][nodes]
+    SBP_GLOBAL double *out;           // SoA [5][nodes]
+    const SBP_GLOBAL double *metric;  // SoA [9][nodes]
+    const SBP_GLOBAL double *jac;     // [nodes]
+    const SBP_GLOBAL int32_t *nbr;    // [K][6]
+    SBP_GLOBAL double *trace;         // viscous face traces [K][6][4][N^2] (mu > 0 only)
+    SBP_GLOBAL double *aux;           // viscous per-node scratch of the plane kernels, [16][nodes]
+    const SBP_GLOBAL double *bc;      // Dirichlet state of boundary faces, SoA [5][nodes], or null
+    const SBP_GLOBAL double *src;     // source added to dq/dt, SoA [5][nodes], or null
+    const SBP_GLOBAL int32_t *orient; // face orientation [K][6] (f' + 8 code), or null (aligned)
+    int *status;                      // sticky flags
     const double *D;       // [N*N] collocation derivative
     long long K;
     long long nodes;

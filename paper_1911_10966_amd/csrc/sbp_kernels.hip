@@ -385,7 +385,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 if (il != 0 && il != N - 1) continue;
                 const int side = (il == N - 1) ? 1 : 0;
                 const int t = tangential_index<N>(l, i1, i2, i3);
-                double *tr = a.trace + ((e * 6 + 2 * l + side) * 4) * N2 + t;
+                SBP_GLOBAL double *tr = a.trace + ((e * 6 + 2 * l + side) * 4) * N2 + t;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) tr[c * N2] = fh[l][c];
                 if (faces & (1 << l)) {
@@ -480,7 +480,7 @@ __device__ __forceinline__ bool visc_fixup_add(const ResArgs &a, long long gl, d
         const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
         const int strd = l == 0 ? 1 : (l == 1 ? N : N2);
         const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * strd);
-        const double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
+        const SBP_GLOBAL double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
         const double cf = 0.5 * s * k.sg / a.w_end;
 #pragma unroll
         for (int c = 0; c < 4; ++c) add[c] = fma(cf, tr[c * N2], add[c]);

@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 a.aux[(AUX_FH + 4 + c) * nodes + gn] = fh[1][c];
             }
             if (i3 == 0 || i3 == N - 1) {
-                double *tr = a.trace + ((e * 6 + 4 + side3) * 4) * N2 + i1 + N * i2;
+                SBP_GLOBAL double *tr = a.trace + ((e * 6 + 4 + side3) * 4) * N2 + i1 + N * i2;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) tr[c * N2] = fh[2][c];
                 if (face3) {
@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_c(const GroupArgs 
 #pragma unroll
             for (int c = 0; c < 4; ++c) fn[c] = k.sg * a.aux[(AUX_FH + 4 * lp + c) * nodes + pg];
         } else {
-            const double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
+            const SBP_GLOBAL double *tr = a.trace + ((nb * 6 + k.fp) * 4) * N2 + k.tp;
 #pragma unroll
             for (int c = 0; c < 4; ++c) fn[c] = k.sg * tr[c * N2];
         }
