@@ -411,12 +411,13 @@ int record_rk_graph(Plan *plan, double *q, const double *dt, char *ws, const Lay
         if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) rc = SBP_ERR_HIP;
     hipGraph_t graph = nullptr;
     if (rc == SBP_OK && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        hipEventRecord(ev.back(), cap);
+        if (hipEventRecord(ev.back(), cap) != hipSuccess) rc = SBP_ERR_HIP;
         for (size_t i = 0; i < br.size() && rc == SBP_OK; ++i) {
-            hipStreamWaitEvent(br[i], ev.back(), 0);
+            if (hipStreamWaitEvent(br[i], ev.back(), 0) != hipSuccess) { rc = SBP_ERR_HIP; break; }
             rc = rk_step_group(plan->groups[i], q, dt, ws, L, br[i]);
-            hipEventRecord(ev[i], br[i]);
-            hipStreamWaitEvent(cap, ev[i], 0);
+            if (rc == SBP_OK && (hipEventRecord(ev[i], br[i]) != hipSuccess ||
+                                 hipStreamWaitEvent(cap, ev[i], 0) != hipSuccess))
+                rc = SBP_ERR_HIP;
         }
         const hipError_t ec = hipStreamEndCapture(cap, &graph);
         if (rc == SBP_OK && (ec != hipSuccess || graph == nullptr)) rc = SBP_ERR_HIP;
@@ -425,12 +426,13 @@ int record_rk_graph(Plan *plan, double *q, const double *dt, char *ws, const Lay
     }
     if (rc == SBP_OK && hipGraphInstantiate(exec, graph, nullptr, nullptr, 0) != hipSuccess)
         rc = SBP_ERR_HIP;
-    if (graph) hipGraphDestroy(graph);
+    // teardown: failures here leave nothing to undo
+    if (graph) (void)hipGraphDestroy(graph);
     for (auto e : ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (auto b : br)
-        if (b) hipStreamDestroy(b);
-    hipStreamDestroy(cap);
+        if (b) (void)hipStreamDestroy(b);
+    (void)hipStreamDestroy(cap);
     return rc;
 }
 
@@ -611,20 +613,23 @@ int sbp_autotune(const sbp_problem *probs, int32_t n_prob, const double *q, doub
         for (int v = 0; v < nv; ++v) {
             rc = residual_group(g, q, dqdt, static_cast<char *>(ws), s, false, v);  // warm-up
             if (rc != SBP_OK) break;
-            hipEventRecord(e0, s);
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = SBP_ERR_HIP; break; }
             for (int r = 0; r < reps && rc == SBP_OK; ++r)
                 rc = residual_group(g, q, dqdt, static_cast<char *>(ws), s, false, v);
-            hipEventRecord(e1, s);
-            if (rc != SBP_OK || hipEventSynchronize(e1) != hipSuccess) { rc = SBP_ERR_HIP; break; }
+            if (rc != SBP_OK || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess) {
+                rc = SBP_ERR_HIP;
+                break;
+            }
             float ms = 0.0f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SBP_ERR_HIP; break; }
             if (v == 0 || ms < best) { best = ms; best_v = v; }
         }
         if (rc != SBP_OK) break;
         g.variant = best_v;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != SBP_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);

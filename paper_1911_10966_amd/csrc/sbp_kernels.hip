@@ -623,10 +623,12 @@ constexpr Schedule kSchedPlanes[] = {{1, 0, 0}, {2, 0, 0}};  // planes per workg
 int device_cus() {
     static int cus = 0;
     if (cus == 0) {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (cus <= 0) cus = 256;
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cus = n;
+        else
+            cus = 256;
     }
     return cus;
 }
@@ -650,10 +652,10 @@ int launch_res_k(const GroupArgs &g, hipStream_t s) {
         if (grid > cap) grid = cap;
     }
     KernelTimer &tm = residual_timer();
-    if (tm.enabled) hipEventRecord(tm.begin, s);
+    if (tm.enabled && hipEventRecord(tm.begin, s) != hipSuccess) return -1;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, g);
     if (hipGetLastError() != hipSuccess) return -1;
-    if (tm.enabled) hipEventRecord(tm.end, s);
+    if (tm.enabled && hipEventRecord(tm.end, s) != hipSuccess) return -1;
     return 0;
 }
 

@@ -657,12 +657,12 @@ int launch_planes_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(PPB * N * N);
     const dim3 grid((unsigned)g.total_blocks);
     KernelTimer &tm = residual_timer();
-    if (tm.enabled) hipEventRecord(tm.begin, s);
+    if (tm.enabled && hipEventRecord(tm.begin, s) != hipSuccess) return -1;
     hipLaunchKernelGGL((k_plane_a<N, PPB, VISC, FLUX, MD>), grid, dim3(NT), 0, s, g);
     hipLaunchKernelGGL((k_plane_b<N, PPB, VISC, FLUX, MD>), grid, dim3(NT), 0, s, g);
     if constexpr (VISC) hipLaunchKernelGGL((k_plane_c<N, PPB>), grid, dim3(NT), 0, s, g);
     if (hipGetLastError() != hipSuccess) return -1;
-    if (tm.enabled) hipEventRecord(tm.end, s);
+    if (tm.enabled && hipEventRecord(tm.end, s) != hipSuccess) return -1;
     return 0;
 }
 
