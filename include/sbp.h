@@ -156,12 +156,14 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
 /* Vector-Jacobian product qbar = (d(dq/dt)/dq)^T gbar of the residual of sbp_residual, with each
  * element recomputing its forward intermediates (no two-point fluxes are stored) and interface
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
- * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0) on periodic problems
- * (bc_state == NULL) with iface_diss 0 or 1; other fluxes, boundary data or matrix dissipation give
- * SBP_ERR_ARG, as does a face_orient table; a boundary face in nbr (any negative entry) raises the mesh flag (SBP_ERR_MESH
- * from sbp_status()) and its terms are left out; degrees above SBP_MAX_VJP_P
- * give SBP_ERR_DEGREE.  A source term does not enter the product.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum
- * in the interface dissipation takes the own side on ties. */
+ * not alias q or gbar.  Available for the Chandrashekar flux (two_point == 0) with iface_diss 0
+ * or 1, on periodic or bounded problems (Dirichlet data is held fixed; wall ghosts are
+ * differentiated through the own state) and with or without a face_orient table; other fluxes or
+ * matrix dissipation give SBP_ERR_ARG, degrees above SBP_MAX_VJP_P give SBP_ERR_DEGREE, and
+ * invalid neighbour or orientation entries raise the mesh flag as in sbp_residual.  A source term
+ * does not enter the product.  Non-smooth points follow fixed conventions: d|x|/dx = +1 at x = 0,
+ * and the maximum in the interface dissipation takes the own side on ties (a wall ghost's speed
+ * equals the own one, so the own side carries it). */
 int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, const double *gbar,
                      double *qbar, void *ws, size_t ws_bytes, void *stream);
 

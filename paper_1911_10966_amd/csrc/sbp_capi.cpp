@@ -535,8 +535,7 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
         return SBP_ERR_ARG;
     for (int b = 0; b < n_prob; ++b) {
-        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].bc_state != nullptr ||
-            probs[b].iface_diss == 2 || probs[b].face_orient != nullptr)
+        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].iface_diss == 2)
             return SBP_ERR_ARG;
         if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
     }
@@ -553,6 +552,8 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
         a.jac = pr.jac;
         a.nbr = pr.nbr;
         a.thb = pr.mu > 0.0 ? reinterpret_cast<double *>(w + L.thb[b]) : nullptr;
+        a.bc = pr.bc_state;
+        a.orient = pr.face_orient;
         a.status = reinterpret_cast<int *>(w);
         a.D = device_D(pr.p);
         if (a.D == nullptr) return SBP_ERR_HIP;

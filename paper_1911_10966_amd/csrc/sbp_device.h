@@ -336,7 +336,8 @@ enum FaceKind : int {
     FACE_WALL = 4,       // nb == -3: adiabatic no-slip wall
 };
 
-__device__ __forceinline__ int face_kind(const ResArgs &a, long long nb) {
+template <class Args>  // ResArgs or VjpArgs
+__device__ __forceinline__ int face_kind(const Args &a, long long nb) {
     if (nb >= 0 && nb < a.K) return FACE_INTERIOR;
     if (nb == -1) return a.bc != nullptr ? FACE_DIRICHLET : FACE_INVALID;
     if (nb == -2) return a.mu == 0.0 ? FACE_SLIP : FACE_INVALID;
@@ -356,8 +357,8 @@ struct FaceLink {
     bool ok;
 };
 
-template <int N, bool ORIENT = true>
-__device__ __forceinline__ FaceLink face_link(const ResArgs &a, long long e, int f, int ta, int tb,
+template <int N, bool ORIENT = true, class Args>  // Args: ResArgs or VjpArgs
+__device__ __forceinline__ FaceLink face_link(const Args &a, long long e, int f, int ta, int tb,
                                               int aligned_lno) {
     FaceLink r;
     r.ok = true;

@@ -129,6 +129,8 @@ struct VjpArgs {
     const double *jac;
     const int32_t *nbr;
     double *thb;           // cotangents of the BR1 gradients, [3][4][nodes] (mu > 0 only)
+    const double *bc;      // Dirichlet state of boundary faces, SoA [5][nodes], or null
+    const int32_t *orient; // face orientation [K][6] (f' + 8 code), or null (aligned faces)
     int *status;
     const double *D;
     long long K;

@@ -359,11 +359,32 @@ k_vjp_visc(const VjpArgs a) {
             const int side = (il == N - 1) ? 1 : 0;
             const double s = side ? 1.0 : -1.0;
             const long long nb = a.nbr[e * 6 + 2 * d + side];
-            if (nb < 0 || nb >= a.K) {
-                atomicOr(a.status, FLAG_MESH);  // boundary faces are not differentiated
+            const int kind = face_kind(a, nb);
+            if (kind == FACE_INVALID) {
+                atomicOr(a.status, FLAG_MESH);
                 continue;
             }
-            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
+            if (kind != FACE_INTERIOR) {
+                // boundary ghost: the prescribed state, or (adiabatic wall) the own state with the
+                // velocity reversed; SAT^V vanishes (Dirichlet) or keeps no energy flux (wall)
+                double wn[4];
+                if (kind == FACE_DIRICHLET) {
+                    NodeFull o;
+                    load_node(a.bc, nodes, g, gm1, a.R, o);
+                    const double iTn = 1.0 / o.T;
+                    wn[0] = o.u[0] * iTn; wn[1] = o.u[1] * iTn; wn[2] = o.u[2] * iTn; wn[3] = -iTn;
+                } else {
+                    wn[0] = -w[0]; wn[1] = -w[1]; wn[2] = -w[2]; wn[3] = w[3];
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) th[d][c] = fma(0.5 * s * isw, wn[c] - w[c], th[d][c]);
+                if (kind == FACE_WALL) fhb[d][3] = fma(-s * isw, rb[3], fhb[d][3]);
+                continue;
+            }
+            const int ta = d == 0 ? i2 : i1, tb = d == 2 ? i2 : i3;
+            const FaceLink k = face_link<N>(a, e, 2 * d + side, ta, tb, ln + (N - 1 - 2 * il) * stride[d]);
+            if (!k.ok) atomicOr(a.status, FLAG_MESH);
+            const long long pg = nb * N3 + k.lno;
             NodeFull o;
             load_node(a.q, nodes, pg, gm1, a.R, o);
             const double iTn = 1.0 / o.T;
@@ -372,7 +393,8 @@ k_vjp_visc(const VjpArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 th[d][c] = fma(0.5 * s * isw, wn[c] - w[c], th[d][c]);
-                // own SAT^V half and the neighbour's SAT^V at the partner node
+                // own SAT^V half and the neighbour's SAT^V at the partner node (the orientation
+                // sign of the neighbour's flux meets its side sign: -s either way)
                 const double rbn = a.gbar[(c + 1) * nodes + pg] * iJn;
                 fhb[d][c] = fma(-0.5 * s * isw, rb[c] + rbn, fhb[d][c]);
             }
@@ -556,21 +578,56 @@ k_vjp_main(const VjpArgs a) {
             const int side = (il == N - 1) ? 1 : 0;
             const double s = side ? 1.0 : -1.0;
             const long long nb = a.nbr[e * 6 + 2 * l + side];
-            if (nb < 0 || nb >= a.K) {
-                atomicOr(a.status, FLAG_MESH);  // boundary faces are not differentiated
+            const int kind = face_kind(a, nb);
+            if (kind == FACE_INVALID) {
+                atomicOr(a.status, FLAG_MESH);
                 continue;
             }
-            const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[l];
-            double qn[5], rbn[5];
-            const double iJn = rcp(a.jac[pg]);
+            const bool bnd = kind != FACE_INTERIOR;
+            // partner: the neighbour's node (its metric row of direction l', signed), or a ghost at
+            // the own node with the own metrics and J; a ghost has no view of its own (rbn = 0)
+            long long pg = g;
+            double An[3] = {A[l][0], A[l][1], A[l][2]};
+            double qn[5], rbn[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            double iJn = iJ;
+            if (!bnd) {
+                const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
+                const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * stride[l]);
+                if (!k.ok) atomicOr(a.status, FLAG_MESH);
+                pg = nb * N3 + k.lno;
+                const int lp = k.fp >> 1;
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                qn[c] = a.q[c * nodes + pg];
-                rbn[c] = a.gbar[c * nodes + pg] * iJn;
+                for (int m = 0; m < 3; ++m) An[m] = k.sg * a.metric[(3 * lp + m) * nodes + pg];
+                iJn = rcp(a.jac[pg]);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    qn[c] = a.q[c * nodes + pg];
+                    rbn[c] = a.gbar[c * nodes + pg] * iJn;
+                }
+            } else if (kind == FACE_DIRICHLET) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
+            } else {
+                qn[0] = q[0];
+                qn[4] = q[4];
+                if (kind == FACE_WALL) {
+                    qn[1] = -q[1]; qn[2] = -q[2]; qn[3] = -q[3];
+                } else {
+                    const double mn = (q[1] * An[0] + q[2] * An[1] + q[3] * An[2]) *
+                                      rcp(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, An[m], q[1 + m]);
+                }
             }
-            double An[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) An[m] = a.metric[(3 * l + m) * nodes + pg];
+            // unit face normal of a slip wall (its ghost reflects the velocity about it)
+            double nh[3] = {0.0, 0.0, 0.0};
+            if (kind == FACE_SLIP) {
+                const double ia = rcp(sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]));
+                nh[0] = An[0] * ia; nh[1] = An[1] * ia; nh[2] = An[2] * ia;
+            }
+            // cotangents of a wall ghost's velocity and temperature, mapped back to the own node
+            // at the end (Dirichlet ghosts do not depend on q)
+            double ugb[3] = {0.0, 0.0, 0.0}, rgb = 0.0, bgb = 0.0;
             Node o;
             double Pn;
             primitives_nolog(qn, gm1, o, Pn);
@@ -585,6 +642,13 @@ k_vjp_main(const VjpArgs a) {
             reduce_bar(me, ab, ra);
 #pragma unroll
             for (int c = 0; c < 5; ++c) acc[c] += ra[c];
+            if (kind == FACE_SLIP || kind == FACE_WALL) {
+                double rg[5];
+                reduce_bar(o, bb, rg);
+                rgb += rg[0];
+                ugb[0] += rg[1]; ugb[1] += rg[2]; ugb[2] += rg[3];
+                bgb += rg[4];
+            }
             if (a.iface_diss) {
                 const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
                 const double unm = me.u1 * n0 + me.u2 * n1 + me.u3 * n2;
@@ -595,20 +659,33 @@ k_vjp_main(const VjpArgs a) {
                 double t_own = 0.0, t_nb = 0.0;
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
-                    qdir[c] -= 0.5 * lam * isw * (rb[c] - rbn[c]);
                     t_own += (q[c] - qn[c]) * rb[c];
                     t_nb += (qn[c] - q[c]) * rbn[c];
                 }
+                // d(q_i - q_ghost)/dq_i: identity (interior, Dirichlet), twice the momentum
+                // (no-slip wall), twice its normal part (slip wall)
+                if (kind == FACE_INTERIOR || kind == FACE_DIRICHLET) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) qdir[c] -= 0.5 * lam * isw * (rb[c] - rbn[c]);
+                } else if (kind == FACE_WALL) {
+#pragma unroll
+                    for (int c = 1; c < 4; ++c) qdir[c] -= lam * isw * rb[c];
+                } else {
+                    const double rn = rb[1] * nh[0] + rb[2] * nh[1] + rb[3] * nh[2];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) qdir[1 + m] -= lam * isw * rn * nh[m];
+                }
                 // lambda depends on this node in the own view when li >= lo (ties go to the own
-                // side) and in the neighbour's view only when li > lo
+                // side) and in the neighbour's view only when li > lo (a wall ghost's speed equals
+                // the own one: the own view carries it)
                 double lb = 0.0;
-                if (li >= lo) lb -= 0.5 * isw * t_own;
+                if (li >= lo || kind == FACE_SLIP || kind == FACE_WALL) lb -= 0.5 * isw * t_own;
                 if (li > lo) lb -= 0.5 * isw * t_nb;
                 if (lb != 0.0) {
-                    const double sg = unm >= 0.0 ? lb : -lb;
-                    acc[1] = fma(sg, n0, acc[1]);
-                    acc[2] = fma(sg, n1, acc[2]);
-                    acc[3] = fma(sg, n2, acc[3]);
+                    const double sgn = unm >= 0.0 ? lb : -lb;
+                    acc[1] = fma(sgn, n0, acc[1]);
+                    acc[2] = fma(sgn, n1, acc[2]);
+                    acc[3] = fma(sgn, n2, acc[3]);
                     const double cb = lb * nn;
                     Pb += cb * a.gamma / (2.0 * cme * me.rho);
                     acc[0] -= cb * cme / (2.0 * me.rho);
@@ -617,7 +694,7 @@ k_vjp_main(const VjpArgs a) {
             if constexpr (VISC) {
                 if (a.eta != 0.0) {
                     // interior penalty X = -(eta/(2 w_end)) [Phi_i(A_i dw/J_i) + Phi_nu(A_nu dw/J_nu)],
-                    // with cotangent rbar_i - rbar_nu (the neighbour's term is -X)
+                    // with cotangent rbar_i - rbar_nu (the neighbour's term is -X; a ghost has none)
                     const double iTn = 2.0 * a.R * o.beta;
                     const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
                     double dw[4], ob[4], dwb[4] = {0.0, 0.0, 0.0, 0.0};
@@ -637,8 +714,31 @@ k_vjp_main(const VjpArgs a) {
                     acc[1] += ubi[0];
                     acc[2] += ubi[1];
                     acc[3] += ubi[2];
+                    if (kind == FACE_WALL) {
+                        // dw = (2 U/T, 0); the ghost's velocity is -U, its temperature the own one
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) wb[c] += dwb[c];
+                        for (int c = 0; c < 3; ++c) wb[c] += 2.0 * dwb[c];
+                        acc[1] -= ubn[0];
+                        acc[2] -= ubn[1];
+                        acc[3] -= ubn[2];
+                        Tb += Tbn;
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) wb[c] += dwb[c];
+                    }
+                }
+            }
+            if (kind == FACE_SLIP || kind == FACE_WALL) {
+                // the ghost's primitives: rho and beta are the own ones, U reversed (no-slip) or
+                // reflected about the face (slip; the reflection is symmetric)
+                acc[0] += rgb;
+                acc[4] += bgb;
+                if (kind == FACE_WALL) {
+                    acc[1] -= ugb[0]; acc[2] -= ugb[1]; acc[3] -= ugb[2];
+                } else {
+                    const double un = ugb[0] * nh[0] + ugb[1] * nh[1] + ugb[2] * nh[2];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) acc[1 + m] += ugb[m] - 2.0 * un * nh[m];
                 }
             }
         }
@@ -675,11 +775,25 @@ k_vjp_main(const VjpArgs a) {
                     const int side = (il == N - 1) ? 1 : 0;
                     const double s = side ? 1.0 : -1.0;
                     const long long nb = a.nbr[e * 6 + 2 * d + side];
-                    if (nb >= 0 && nb < a.K) {
-                        const long long pg = nb * N3 + ln + (N - 1 - 2 * il) * stride[d];
+                    const int kind = face_kind(a, nb);
+                    if (kind == FACE_INTERIOR) {
+                        // own SAT^theta and the neighbour's (its direction l', signed) at the partner
+                        const int ta = d == 0 ? i2 : i1, tb = d == 2 ? i2 : i3;
+                        const FaceLink k = face_link<N>(a, e, 2 * d + side, ta, tb,
+                                                        ln + (N - 1 - 2 * il) * stride[d]);
+                        const long long pg = nb * N3 + k.lno;
+                        const int dp = k.fp >> 1;
 #pragma unroll
                         for (int c = 0; c < 4; ++c)
-                            wb[c] = fma(-0.5 * s * isw, thb_me[c] + a.thb[(d * 4 + c) * nodes + pg], wb[c]);
+                            wb[c] = fma(-0.5 * s * isw, thb_me[c] + k.sg * a.thb[(dp * 4 + c) * nodes + pg],
+                                        wb[c]);
+                    } else if (kind == FACE_DIRICHLET) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) wb[c] = fma(-0.5 * s * isw, thb_me[c], wb[c]);
+                    } else if (kind == FACE_WALL) {
+                        // w_ghost - w_i = (-2 U/T, 0)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) wb[c] = fma(-s * isw, thb_me[c], wb[c]);
                     }
                 }
             }

@@ -115,12 +115,3 @@ def test_boundary_without_data_is_a_mesh_error():
     ps.residual(to_dev(c.q))
     with pytest.raises(P.SBPError):
         ps.status()
-
-
-def test_vjp_rejects_boundary_problems():
-    require_gpu()
-    c = _mms_case(2, 2, 0.0)
-    ps = P.ProblemSet([_dev_problem(c)])
-    q = to_dev(c.q)
-    with pytest.raises(P.SBPError):
-        ps.residual_vjp(q, torch.ones_like(q))

@@ -2,7 +2,7 @@
 face table (neighbour face and orientation) found from the coordinates.  Parity with the oracle on
 every kernel path (per-node faces N <= 5, face work items N = 6..8, plane passes N >= 10), with
 walls, matrix dissipation and the SF-KG form; invariance against the aligned mesh at a larger size;
-an RK4 step; and the errors (VJP, invalid table entries)."""
+an RK4 step; and invalid table entries (the VJP on such meshes: test_gpu_vjp_boundaries)."""
 import numpy as np
 import pytest
 import torch
@@ -126,15 +126,6 @@ def test_rotated_mesh_rk4_step():
     f = lambda y: R.residual(y, c.metric, c.jac, c.nbr, c.sbp, c.prm, orient=c.orient)  # noqa: E731
     ref = R.rk4_step(f, c.q, 2e-3)
     assert rel_err(out - c.q, ref - c.q) < 1e-10
-
-
-def test_vjp_rejects_an_orientation_table():
-    require_gpu()
-    c = RotCase(W.make_problem(p=2, E=2, L=2.0, A=0.1, seed=1, u_rms=0.3), seed=1)
-    ps = P.ProblemSet([c.device()])
-    q = to_dev(c.q)
-    with pytest.raises(P.SBPError):
-        ps.residual_vjp(q, torch.ones_like(q))
 
 
 def test_invalid_orientation_entry_is_a_mesh_error():

@@ -1,0 +1,157 @@
+"""Hand-written VJP with boundary faces (Dirichlet, slip wall, adiabatic no-slip wall) and on
+unstructured meshes (face-orientation table), against the oracle: the extended-precision
+complex-step Jacobian on small meshes, the dot-product identity gbar.(J v) = qbar.v with the
+oracle's complex-step J v for p up to 8, and central differences of the GPU residual."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1911_10966_amd as P
+import workloads as W
+from workloads import unstructured as U
+from gpu_helpers import DEV, device_problem, from_dev, require_gpu, to_dev
+from helpers import Case, rel_err
+from oracle import geometry, jvp, operators, residual as R
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+class BCase:
+    """A problem with boundary kinds per box direction, or with every element turned by a random
+    rotation of the cube (face table from the coordinates)."""
+
+    def __init__(self, p, E, mu, box=(None, None, None), rotate=False, seed=1, diss=1, eta=1.0):
+        prob = W.make_problem(p=p, E=E, L=2.0, A=0.1, mu=mu, iface_diss=diss, eta=eta, seed=seed,
+                              u_rms=0.3, box=box)
+        c = Case(prob)
+        self.prob, self.sbp, self.prm = prob, c.sbp, c.prm
+        self.q = c.jumpy(0.02, seed + 1)
+        self.x, self.metric, self.jac = c.x, c.metric, c.jac
+        self.nbr, self.orient = W.problem_neighbours(prob), None
+        if rotate:
+            rots = np.random.Generator(np.random.PCG64(seed + 2)).integers(0, 24, prob.K)
+            self.x = U.rotate_elements(c.x, rots)
+            self.q = U.rotate_elements(self.q, rots)
+            self.metric = geometry.curl_metrics(self.x, self.sbp.D)
+            self.jac = geometry.jacobian(self.x, self.sbp.D)
+            periods = tuple(None if b is not None else prob.L for b in box)
+            kinds = {b for b in box if b is not None}
+            self.nbr, self.orient = U.connectivity(self.x, prob.L, boundary=kinds.pop() if kinds else -1,
+                                                   periods=periods)
+        # Dirichlet data with noise of its own (no ties with the state in the dissipation's maximum)
+        rng = np.random.Generator(np.random.PCG64(seed + 3))
+        self.bc = self.q * (1.0 + 0.03 * rng.standard_normal(self.q.shape)) if -1 in box else None
+
+    def kw(self):
+        return {"bc": self.bc, "orient": self.orient}
+
+    def device(self):
+        pr = self.prob
+        return P.Problem(p=pr.p, n_elem=pr.K, nbr=torch.as_tensor(self.nbr, device=DEV).contiguous(),
+                         metric=to_dev(self.metric).reshape(9, -1), jac=to_dev(self.jac),
+                         gamma=pr.gamma, R=pr.R, mu=pr.mu, Pr=pr.Pr, eta=pr.eta,
+                         iface_diss=pr.iface_diss, two_point=pr.two_point,
+                         bc_state=None if self.bc is None else to_dev(self.bc),
+                         face_orient=None if self.orient is None else
+                         torch.as_tensor(self.orient, device=DEV).contiguous())
+
+    def vjp(self, q, gb):
+        ps = P.ProblemSet([self.device()])
+        out = from_dev(ps.residual_vjp(to_dev(q), to_dev(gb)), q.shape)
+        assert ps.status() == 0
+        return out
+
+
+FULL = [
+    # p, E, mu, box, rotate
+    (1, 2, 0.03, (-3, None, None), False),
+    (1, 2, 0.0, (-2, None, -2), False),
+    (1, 2, 0.02, (-1, -3, None), False),
+    (1, 2, 0.02, (None, None, None), True),
+    (2, 2, 0.02, (None, -3, None), True),
+]
+
+
+@pytest.mark.parametrize("p,E,mu,box,rotate", FULL)
+def test_boundary_vjp_matches_full_jacobian(p, E, mu, box, rotate):
+    require_gpu()
+    print(f"vjp full jacobian p={p} E={E} mu={mu} box={box} rotate={rotate}", flush=True)
+    c = BCase(p, E, mu, box, rotate, seed=10 * p + E)
+    LD = np.longdouble
+    kw = c.kw()
+    if kw["bc"] is not None:
+        kw["bc"] = kw["bc"].astype(LD)
+    Jm = jvp.full_jacobian(c.q, c.metric.astype(LD), c.jac.astype(LD), c.nbr, operators.SBP1D(p, LD),
+                           c.prm, ctype=np.clongdouble, **kw)
+    rng = np.random.Generator(np.random.PCG64(3))
+    gb = rng.standard_normal(c.q.shape)
+    ref = (Jm.T @ gb.ravel().astype(LD)).reshape(c.q.shape).astype(np.float64)
+    err = rel_err(c.vjp(c.q, gb), ref)
+    print(f"  gpu vs extended-precision J^T gbar: {err:.2e}")
+    assert err < TOL
+
+
+DOT = [
+    # p, E, mu, box, rotate, iface_diss
+    (3, 2, 0.02, (-3, None, -3), False, 1),
+    (4, 2, 0.0, (-2, -2, None), False, 1),
+    (4, 2, 0.01, (-1, None, -3), False, 0),
+    (5, 2, 0.01, (None, None, None), True, 1),
+    (6, 2, 0.01, (None, -3, None), True, 1),
+    (7, 2, 0.0, (-2, None, None), True, 1),
+    (8, 2, 0.01, (-3, -1, -3), False, 1),
+]
+
+
+@pytest.mark.parametrize("p,E,mu,box,rotate,diss", DOT)
+def test_boundary_vjp_dot_product_with_complex_step_jvp(p, E, mu, box, rotate, diss):
+    require_gpu()
+    print(f"vjp dot p={p} E={E} mu={mu} box={box} rotate={rotate} diss={diss}", flush=True)
+    c = BCase(p, E, mu, box, rotate, seed=p, diss=diss)
+    rng = np.random.Generator(np.random.PCG64(p))
+    gb = rng.standard_normal(c.q.shape)
+    v = W.direction(torch.as_tensor(c.q), 5).numpy()
+    jv = jvp.jvp(c.q, v, c.metric, c.jac, c.nbr, c.sbp, c.prm, **c.kw())
+    qb = c.vjp(c.q, gb)
+    lhs, rhs = (gb * jv).sum(), (qb * v).sum()
+    scale = np.abs(gb * jv).sum()
+    print(f"  dot: rel {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) < TOL * scale
+
+
+def test_boundary_vjp_central_difference():
+    require_gpu()
+    c = BCase(4, 2, 0.02, (-3, -1, None), False, seed=9)
+    gb = np.random.Generator(np.random.PCG64(9)).standard_normal(c.q.shape)
+    v = W.direction(torch.as_tensor(c.q), 6).numpy()
+    ps = P.ProblemSet([c.device()])
+    h = 1e-6
+    rp = from_dev(ps.residual(to_dev(c.q + h * v)), c.q.shape)
+    rm = from_dev(ps.residual(to_dev(c.q - h * v)), c.q.shape)
+    fd = (gb * (rp - rm)).sum() / (2 * h)
+    qb = c.vjp(c.q, gb)
+    assert abs(fd - (qb * v).sum()) < 1e-6 * np.abs(gb * (rp - rm) / (2 * h)).sum()
+
+
+def test_vjp_ignores_the_source_term():
+    require_gpu()
+    c = BCase(2, 2, 0.02, (-1, None, None), False, seed=4)
+    gb = np.random.Generator(np.random.PCG64(4)).standard_normal(c.q.shape)
+    a = c.vjp(c.q, gb)
+    dp = c.device()
+    dp.source = to_dev(np.ones_like(c.q))
+    ps = P.ProblemSet([dp])
+    b = from_dev(ps.residual_vjp(to_dev(c.q), to_dev(gb)), c.q.shape)
+    assert ps.status() == 0
+    assert np.array_equal(a, b)
+
+
+def test_vjp_flags_a_slip_wall_on_a_viscous_problem():
+    require_gpu()
+    c = BCase(2, 2, 0.01, (-2, None, None), False, seed=5)
+    ps = P.ProblemSet([c.device()])
+    q = to_dev(c.q)
+    ps.residual_vjp(q, torch.ones_like(q))
+    with pytest.raises(P.SBPError):
+        ps.status()

@@ -1,7 +1,8 @@
 """GPU residual with wall boundary faces (slip -2, adiabatic no-slip -3, mixed with Dirichlet -1)
 against the oracle, element by element, on every kernel path: per-node faces (N <= 5), face work
 items (N = 6..8), the plane passes (N >= 10), matrix dissipation, the SF-KG and DC forms; then an
-RK4 step, a batch mixing wall and periodic problems, conservation at a large size, and the errors."""
+RK4 step, a batch mixing wall and periodic problems, conservation at a large size, and the errors
+(the VJP with walls: test_gpu_vjp_boundaries)."""
 import numpy as np
 import pytest
 import torch
@@ -135,15 +136,5 @@ def test_slip_wall_on_a_viscous_problem_is_a_mesh_error():
     c = _case(2, 2, 0.0, (-2, None, None), 0.01, 1, 0)
     ps = P.ProblemSet([_dev_problem(c)])
     ps.residual(to_dev(c.q))
-    with pytest.raises(P.SBPError):
-        ps.status()
-
-
-def test_vjp_flags_wall_faces():
-    require_gpu()
-    c = _case(2, 2, 0.0, (-3, None, None), 0.0, 1, 0)
-    ps = P.ProblemSet([_dev_problem(c)])
-    q = to_dev(c.q)
-    ps.residual_vjp(q, torch.ones_like(q))
     with pytest.raises(P.SBPError):
         ps.status()
