@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -436,6 +437,18 @@ int record_rk_graph(Plan *plan, double *q, const double *dt, char *ws, const Lay
     return rc;
 }
 
+// Marks that tell the VJP's boundary pass whether its launch met a boundary face (the workspace's
+// second flag word holds the last mark written; never 0).
+int next_vjp_mark() {
+    static std::atomic<int> mark{0};
+    int m = mark.fetch_add(1) + 1;
+    if (m <= 0) {
+        mark.store(1);
+        m = 1;
+    }
+    return m;
+}
+
 }  // namespace
 
 extern "C" {
@@ -555,6 +568,8 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
         a.bc = pr.bc_state;
         a.orient = pr.face_orient;
         a.status = reinterpret_cast<int *>(w);
+        a.bnd_seen = reinterpret_cast<int *>(w) + 1;
+        a.gen = next_vjp_mark();
         a.D = device_D(pr.p);
         if (a.D == nullptr) return SBP_ERR_HIP;
         a.K = pr.n_elem;

@@ -132,6 +132,8 @@ struct VjpArgs {
     const double *bc;      // Dirichlet state of boundary faces, SoA [5][nodes], or null
     const int32_t *orient; // face orientation [K][6] (f' + 8 code), or null (aligned faces)
     int *status;
+    int *bnd_seen;         // set to `gen` by the pass that meets a boundary face
+    int gen;               // this launch's mark (distinct per launch)
     const double *D;
     long long K;
     long long nodes;

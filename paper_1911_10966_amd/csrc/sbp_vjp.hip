@@ -428,11 +428,143 @@ k_vjp_visc(const VjpArgs a) {
     }
 }
 
+// Reverse of the interface terms (EC flux, dissipation, interior penalty) at one face node with
+// outward sign s, partner state qn with metric row An and 1/J iJn, and partner cotangent rbn (the
+// partner's own view of the same pair; zero for a boundary ghost).  BND: the partner is a boundary
+// ghost of kind `kind` (Dirichlet data is a constant; a wall ghost is the own state with the
+// momentum reversed or reflected, differentiated through the own state).  Accumulates the
+// cotangents of the own node's (rho, U, beta) in acc, of P and T, of q directly (qdir), and of the
+// entropy variables (wb).
+template <bool VISC, bool BND>
+__device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, const double q[5],
+                                              const double rb[5], const double Al[3], double iJ,
+                                              double Pme, double Tme, const double wme[4], double s,
+                                              int kind, const double qn[5], const double rbn[5],
+                                              const double An[3], double iJn, double acc[5],
+                                              double &Pb, double &Tb, double qdir[5], double wb[4]) {
+    const double gm1 = a.gamma - 1.0;
+    const double isw = 1.0 / a.w_end;
+    const double mu = a.mu;
+    const double kap = a.mu * a.gamma * a.R / ((a.gamma - 1.0) * a.Pr);
+    Node o;
+    double Pn;
+    primitives_nolog(qn, gm1, o, Pn);
+    const double n0 = 0.5 * (Al[0] + An[0]), n1 = 0.5 * (Al[1] + An[1]),
+                 n2 = 0.5 * (Al[2] + An[2]);
+    double fb[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) fb[c] = -s * isw * (rb[c] - rbn[c]);
+    NodeBar ab, bb;
+    flux_n_vjp<true>(me, o, n0, n1, n2, gm1, fb, ab, bb);
+    double ra[5];
+    reduce_bar(me, ab, ra);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] += ra[c];
+    if (BND && (kind == FACE_SLIP || kind == FACE_WALL)) {
+        // a wall ghost's primitives: rho and beta are the own ones, U reversed (no-slip) or
+        // reflected about the face (slip; the reflection is symmetric)
+        double rg[5];
+        reduce_bar(o, bb, rg);
+        acc[0] += rg[0];
+        acc[4] += rg[4];
+        if (kind == FACE_WALL) {
+            acc[1] -= rg[1]; acc[2] -= rg[2]; acc[3] -= rg[3];
+        } else {
+            const double ia2 = rcp(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
+            const double un = (rg[1] * An[0] + rg[2] * An[1] + rg[3] * An[2]) * ia2;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) acc[1 + m] += rg[1 + m] - 2.0 * un * An[m];
+        }
+    }
+    if (a.iface_diss) {
+        const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double unm = me.u1 * n0 + me.u2 * n1 + me.u3 * n2;
+        const double cme = sqrt(a.gamma * Pme / me.rho);
+        const double li = fabs(unm) + cme * nn;
+        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
+        const double lam = fmax(li, lo);
+        double t_own = 0.0, t_nb = 0.0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            t_own += (q[c] - qn[c]) * rb[c];
+            t_nb += (qn[c] - q[c]) * rbn[c];
+        }
+        // d(q_i - q_ghost)/dq_i: identity (interior, Dirichlet), twice the momentum
+        // (no-slip wall), twice its normal part (slip wall)
+        if (!BND || kind == FACE_DIRICHLET) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) qdir[c] -= 0.5 * lam * isw * (rb[c] - rbn[c]);
+        } else if (kind == FACE_WALL) {
+#pragma unroll
+            for (int c = 1; c < 4; ++c) qdir[c] -= lam * isw * rb[c];
+        } else {
+            // twice the projection on the face normal An
+            const double rn = (rb[1] * An[0] + rb[2] * An[1] + rb[3] * An[2]) *
+                              rcp(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) qdir[1 + m] -= lam * isw * rn * An[m];
+        }
+        // lambda depends on this node in the own view when li >= lo (ties go to the own
+        // side) and in the neighbour's view only when li > lo (a wall ghost's speed equals
+        // the own one: the own view carries it)
+        double lb = 0.0;
+        if (li >= lo || (BND && kind != FACE_DIRICHLET)) lb -= 0.5 * isw * t_own;
+        if (li > lo) lb -= 0.5 * isw * t_nb;
+        if (lb != 0.0) {
+            const double sgn = unm >= 0.0 ? lb : -lb;
+            acc[1] = fma(sgn, n0, acc[1]);
+            acc[2] = fma(sgn, n1, acc[2]);
+            acc[3] = fma(sgn, n2, acc[3]);
+            const double cb = lb * nn;
+            Pb += cb * a.gamma / (2.0 * cme * me.rho);
+            acc[0] -= cb * cme / (2.0 * me.rho);
+        }
+    }
+    if constexpr (VISC) {
+        if (a.eta != 0.0) {
+            // interior penalty X = -(eta/(2 w_end)) [Phi_i(A_i dw/J_i) + Phi_nu(A_nu dw/J_nu)],
+            // with cotangent rbar_i - rbar_nu (the neighbour's term is -X; a ghost has none)
+            const double iTn = 2.0 * a.R * o.beta;
+            const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
+            double dw[4], ob[4], dwb[4] = {0.0, 0.0, 0.0, 0.0};
+            const double cf = -0.5 * a.eta * isw;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                dw[c] = wme[c] - wn[c];
+                ob[c] = cf * (rb[c + 1] - rbn[c + 1]);
+            }
+            const double umv[3] = {me.u1, me.u2, me.u3};
+            const double unv[3] = {o.u1, o.u2, o.u3};
+            double ubi[3] = {0.0, 0.0, 0.0}, ubn[3] = {0.0, 0.0, 0.0}, Tbn = 0.0;
+            visc_flux_rank1_vjp(Al[0], Al[1], Al[2], iJ, dw, umv, Tme, mu, kap, ob, dwb,
+                                ubi, Tb);
+            visc_flux_rank1_vjp(An[0], An[1], An[2], iJn, dw, unv, rcp(iTn), mu, kap, ob, dwb,
+                                ubn, Tbn);
+            acc[1] += ubi[0];
+            acc[2] += ubi[1];
+            acc[3] += ubi[2];
+            if (BND && kind == FACE_WALL) {
+                // dw = (2 U/T, 0); the ghost's velocity is -U, its temperature the own one
+#pragma unroll
+                for (int c = 0; c < 3; ++c) wb[c] += 2.0 * dwb[c];
+                acc[1] -= ubn[0];
+                acc[2] -= ubn[1];
+                acc[3] -= ubn[2];
+                Tb += Tbn;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wb[c] += dwb[c];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Pass 2: everything else; adds to the partial qbar of pass 1 when VISC.
 // ------------------------------------------------------------------------------------------
-template <int N, int EPW, bool VISC>
+template <int N, int EPW, bool VISC, bool OR>
 __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
+__attribute__((amdgpu_waves_per_eu(OR ? 2 : 1, 8)))  // the orientation lookup would cost a wave
 k_vjp_main(const VjpArgs a) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
     constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6, F_K = 7;
@@ -583,164 +715,27 @@ k_vjp_main(const VjpArgs a) {
                 atomicOr(a.status, FLAG_MESH);
                 continue;
             }
-            const bool bnd = kind != FACE_INTERIOR;
-            // partner: the neighbour's node (its metric row of direction l', signed), or a ghost at
-            // the own node with the own metrics and J; a ghost has no view of its own (rbn = 0)
-            long long pg = g;
-            double An[3] = {A[l][0], A[l][1], A[l][2]};
-            double qn[5], rbn[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            double iJn = iJ;
-            if (!bnd) {
-                const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
-                const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * stride[l]);
-                if (!k.ok) atomicOr(a.status, FLAG_MESH);
-                pg = nb * N3 + k.lno;
-                const int lp = k.fp >> 1;
-#pragma unroll
-                for (int m = 0; m < 3; ++m) An[m] = k.sg * a.metric[(3 * lp + m) * nodes + pg];
-                iJn = rcp(a.jac[pg]);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    qn[c] = a.q[c * nodes + pg];
-                    rbn[c] = a.gbar[c * nodes + pg] * iJn;
-                }
-            } else if (kind == FACE_DIRICHLET) {
-#pragma unroll
-                for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
-            } else {
-                qn[0] = q[0];
-                qn[4] = q[4];
-                if (kind == FACE_WALL) {
-                    qn[1] = -q[1]; qn[2] = -q[2]; qn[3] = -q[3];
-                } else {
-                    const double mn = (q[1] * An[0] + q[2] * An[1] + q[3] * An[2]) *
-                                      rcp(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, An[m], q[1 + m]);
-                }
+            if (kind != FACE_INTERIOR) {
+                atomicExch(a.bnd_seen, a.gen);  // boundary faces: k_vjp_bnd
+                continue;
             }
-            // unit face normal of a slip wall (its ghost reflects the velocity about it)
-            double nh[3] = {0.0, 0.0, 0.0};
-            if (kind == FACE_SLIP) {
-                const double ia = rcp(sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]));
-                nh[0] = An[0] * ia; nh[1] = An[1] * ia; nh[2] = An[2] * ia;
+            // partner: the neighbour's node, with its metric row of direction l' (signed)
+            const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
+            const FaceLink k = face_link<N, OR>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * stride[l]);
+            if (!k.ok) atomicOr(a.status, FLAG_MESH);
+            const long long pg = nb * N3 + k.lno;
+            const int lp = k.fp >> 1;
+            double An[3], qn[5], rbn[5];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) An[m] = k.sg * a.metric[(3 * lp + m) * nodes + pg];
+            const double iJn = rcp(a.jac[pg]);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                qn[c] = a.q[c * nodes + pg];
+                rbn[c] = a.gbar[c * nodes + pg] * iJn;
             }
-            // cotangents of a wall ghost's velocity and temperature, mapped back to the own node
-            // at the end (Dirichlet ghosts do not depend on q)
-            double ugb[3] = {0.0, 0.0, 0.0}, rgb = 0.0, bgb = 0.0;
-            Node o;
-            double Pn;
-            primitives_nolog(qn, gm1, o, Pn);
-            const double n0 = 0.5 * (A[l][0] + An[0]), n1 = 0.5 * (A[l][1] + An[1]),
-                         n2 = 0.5 * (A[l][2] + An[2]);
-            double fb[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) fb[c] = -s * isw * (rb[c] - rbn[c]);
-            NodeBar ab, bb;
-            flux_n_vjp<true>(me, o, n0, n1, n2, gm1, fb, ab, bb);
-            double ra[5];
-            reduce_bar(me, ab, ra);
-#pragma unroll
-            for (int c = 0; c < 5; ++c) acc[c] += ra[c];
-            if (kind == FACE_SLIP || kind == FACE_WALL) {
-                double rg[5];
-                reduce_bar(o, bb, rg);
-                rgb += rg[0];
-                ugb[0] += rg[1]; ugb[1] += rg[2]; ugb[2] += rg[3];
-                bgb += rg[4];
-            }
-            if (a.iface_diss) {
-                const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-                const double unm = me.u1 * n0 + me.u2 * n1 + me.u3 * n2;
-                const double cme = sqrt(a.gamma * Pme / me.rho);
-                const double li = fabs(unm) + cme * nn;
-                const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
-                const double lam = fmax(li, lo);
-                double t_own = 0.0, t_nb = 0.0;
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    t_own += (q[c] - qn[c]) * rb[c];
-                    t_nb += (qn[c] - q[c]) * rbn[c];
-                }
-                // d(q_i - q_ghost)/dq_i: identity (interior, Dirichlet), twice the momentum
-                // (no-slip wall), twice its normal part (slip wall)
-                if (kind == FACE_INTERIOR || kind == FACE_DIRICHLET) {
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) qdir[c] -= 0.5 * lam * isw * (rb[c] - rbn[c]);
-                } else if (kind == FACE_WALL) {
-#pragma unroll
-                    for (int c = 1; c < 4; ++c) qdir[c] -= lam * isw * rb[c];
-                } else {
-                    const double rn = rb[1] * nh[0] + rb[2] * nh[1] + rb[3] * nh[2];
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) qdir[1 + m] -= lam * isw * rn * nh[m];
-                }
-                // lambda depends on this node in the own view when li >= lo (ties go to the own
-                // side) and in the neighbour's view only when li > lo (a wall ghost's speed equals
-                // the own one: the own view carries it)
-                double lb = 0.0;
-                if (li >= lo || kind == FACE_SLIP || kind == FACE_WALL) lb -= 0.5 * isw * t_own;
-                if (li > lo) lb -= 0.5 * isw * t_nb;
-                if (lb != 0.0) {
-                    const double sgn = unm >= 0.0 ? lb : -lb;
-                    acc[1] = fma(sgn, n0, acc[1]);
-                    acc[2] = fma(sgn, n1, acc[2]);
-                    acc[3] = fma(sgn, n2, acc[3]);
-                    const double cb = lb * nn;
-                    Pb += cb * a.gamma / (2.0 * cme * me.rho);
-                    acc[0] -= cb * cme / (2.0 * me.rho);
-                }
-            }
-            if constexpr (VISC) {
-                if (a.eta != 0.0) {
-                    // interior penalty X = -(eta/(2 w_end)) [Phi_i(A_i dw/J_i) + Phi_nu(A_nu dw/J_nu)],
-                    // with cotangent rbar_i - rbar_nu (the neighbour's term is -X; a ghost has none)
-                    const double iTn = 2.0 * a.R * o.beta;
-                    const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
-                    double dw[4], ob[4], dwb[4] = {0.0, 0.0, 0.0, 0.0};
-                    const double cf = -0.5 * a.eta * isw;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        dw[c] = wme[c] - wn[c];
-                        ob[c] = cf * (rb[c + 1] - rbn[c + 1]);
-                    }
-                    const double umv[3] = {me.u1, me.u2, me.u3};
-                    const double unv[3] = {o.u1, o.u2, o.u3};
-                    double ubi[3] = {0.0, 0.0, 0.0}, ubn[3] = {0.0, 0.0, 0.0}, Tbn = 0.0;
-                    visc_flux_rank1_vjp(A[l][0], A[l][1], A[l][2], iJ, dw, umv, Tme, mu, kap, ob, dwb,
-                                        ubi, Tb);
-                    visc_flux_rank1_vjp(An[0], An[1], An[2], iJn, dw, unv, rcp(iTn), mu, kap, ob, dwb,
-                                        ubn, Tbn);
-                    acc[1] += ubi[0];
-                    acc[2] += ubi[1];
-                    acc[3] += ubi[2];
-                    if (kind == FACE_WALL) {
-                        // dw = (2 U/T, 0); the ghost's velocity is -U, its temperature the own one
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) wb[c] += 2.0 * dwb[c];
-                        acc[1] -= ubn[0];
-                        acc[2] -= ubn[1];
-                        acc[3] -= ubn[2];
-                        Tb += Tbn;
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) wb[c] += dwb[c];
-                    }
-                }
-            }
-            if (kind == FACE_SLIP || kind == FACE_WALL) {
-                // the ghost's primitives: rho and beta are the own ones, U reversed (no-slip) or
-                // reflected about the face (slip; the reflection is symmetric)
-                acc[0] += rgb;
-                acc[4] += bgb;
-                if (kind == FACE_WALL) {
-                    acc[1] -= ugb[0]; acc[2] -= ugb[1]; acc[3] -= ugb[2];
-                } else {
-                    const double un = ugb[0] * nh[0] + ugb[1] * nh[1] + ugb[2] * nh[2];
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) acc[1 + m] += ugb[m] - 2.0 * un * nh[m];
-                }
-            }
+            face_term_vjp<VISC, false>(a, me, q, rb, A[l], iJ, Pme, Tme, wme, s, kind, qn, rbn, An, iJn,
+                                       acc, Pb, Tb, qdir, wb);
         }
     }
 
@@ -775,25 +770,17 @@ k_vjp_main(const VjpArgs a) {
                     const int side = (il == N - 1) ? 1 : 0;
                     const double s = side ? 1.0 : -1.0;
                     const long long nb = a.nbr[e * 6 + 2 * d + side];
-                    const int kind = face_kind(a, nb);
-                    if (kind == FACE_INTERIOR) {
+                    if (face_kind(a, nb) == FACE_INTERIOR) {
                         // own SAT^theta and the neighbour's (its direction l', signed) at the partner
                         const int ta = d == 0 ? i2 : i1, tb = d == 2 ? i2 : i3;
-                        const FaceLink k = face_link<N>(a, e, 2 * d + side, ta, tb,
-                                                        ln + (N - 1 - 2 * il) * stride[d]);
+                        const FaceLink k = face_link<N, OR>(a, e, 2 * d + side, ta, tb,
+                                                            ln + (N - 1 - 2 * il) * stride[d]);
                         const long long pg = nb * N3 + k.lno;
                         const int dp = k.fp >> 1;
 #pragma unroll
                         for (int c = 0; c < 4; ++c)
                             wb[c] = fma(-0.5 * s * isw, thb_me[c] + k.sg * a.thb[(dp * 4 + c) * nodes + pg],
                                         wb[c]);
-                    } else if (kind == FACE_DIRICHLET) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) wb[c] = fma(-0.5 * s * isw, thb_me[c], wb[c]);
-                    } else if (kind == FACE_WALL) {
-                        // w_ghost - w_i = (-2 U/T, 0)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) wb[c] = fma(-s * isw, thb_me[c], wb[c]);
                     }
                 }
             }
@@ -819,18 +806,136 @@ k_vjp_main(const VjpArgs a) {
     }
 }
 
-template <int N, int EPW>
-int launch_vjp_n(const VjpArgs &a, hipStream_t s) {
+// ------------------------------------------------------------------------------------------
+// Pass 3: boundary faces (Dirichlet, slip and no-slip walls), one thread per node; adds to qbar.
+// Kept out of pass 2 so that its registers do not lower that kernel's occupancy.
+// ------------------------------------------------------------------------------------------
+template <int N, bool VISC>
+__global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
+    constexpr int N2 = N * N, N3 = N * N * N;
+    // nothing to do unless the main pass met a boundary face in this launch
+    if (__hip_atomic_load(a.bnd_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.gen) return;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nodes) return;
+    const long long e = g / N3;
+    const int ln = (int)(g - e * N3);
+    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+    const int idx[3] = {i1, i2, i3};
+    int kinds[3] = {FACE_INTERIOR, FACE_INTERIOR, FACE_INTERIOR};
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int il = idx[l];
+        if (il != 0 && il != N - 1) continue;
+        const int k = face_kind(a, a.nbr[e * 6 + 2 * l + (il == N - 1 ? 1 : 0)]);
+        if (k >= FACE_DIRICHLET) {
+            kinds[l] = k;
+            any = true;
+        }
+    }
+    if (!any) return;
+    const long long nodes = a.nodes;
+    const double gm1 = a.gamma - 1.0;
+    const double isw = 1.0 / a.w_end;
+    double q[5], rb[5];
+    const double iJ = rcp(a.jac[g]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        q[c] = a.q[c * nodes + g];
+        rb[c] = a.gbar[c * nodes + g] * iJ;
+    }
+    Node me;
+    double Pme;
+    bool ok;
+    primitives(q, gm1, me, Pme, ok);
+    const double Tme = 0.5 / (a.R * me.beta);
+    double wme[4] = {0.0, 0.0, 0.0, 0.0};
+    if (VISC) {
+        const double iT = 1.0 / Tme;
+        wme[0] = me.u1 * iT; wme[1] = me.u2 * iT; wme[2] = me.u3 * iT; wme[3] = -iT;
+    }
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, qdir[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double wb[4] = {0.0, 0.0, 0.0, 0.0};
+    double Pb = 0.0, Tb = 0.0;
+    const double zero[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int kind = kinds[l];
+        if (kind == FACE_INTERIOR) continue;
+        const double s = idx[l] == N - 1 ? 1.0 : -1.0;
+        double Al[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) Al[m] = a.metric[(3 * l + m) * nodes + g];
+        // the ghost state (own metrics and J)
+        double qn[5];
+        if (kind == FACE_DIRICHLET) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
+        } else {
+            qn[0] = q[0];
+            qn[4] = q[4];
+            if (kind == FACE_WALL) {
+                qn[1] = -q[1]; qn[2] = -q[2]; qn[3] = -q[3];
+            } else {
+                const double mn = (q[1] * Al[0] + q[2] * Al[1] + q[3] * Al[2]) *
+                                  rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, Al[m], q[1 + m]);
+            }
+        }
+        face_term_vjp<VISC, true>(a, me, q, rb, Al, iJ, Pme, Tme, wme, s, kind, qn, zero, Al, iJ, acc, Pb,
+                                  Tb, qdir, wb);
+        if constexpr (VISC) {
+            // transposed SAT^theta of the boundary face: (s/(2 w_end)) (w_ghost - w_i)
+            double thb_me[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) thb_me[c] = a.thb[(l * 4 + c) * nodes + g];
+            if (kind == FACE_DIRICHLET) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wb[c] = fma(-0.5 * s * isw, thb_me[c], wb[c]);
+            } else if (kind == FACE_WALL) {
+                // w_ghost - w_i = (-2 U/T, 0)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) wb[c] = fma(-s * isw, thb_me[c], wb[c]);
+            }
+        }
+    }
+    if constexpr (VISC) {
+        const double iT = 1.0 / Tme;
+        acc[1] = fma(wb[0], iT, acc[1]);
+        acc[2] = fma(wb[1], iT, acc[2]);
+        acc[3] = fma(wb[2], iT, acc[3]);
+        Tb += (-(wb[0] * me.u1 + wb[1] * me.u2 + wb[2] * me.u3) + wb[3]) * iT * iT;
+    }
+    double ub[3] = {acc[1], acc[2], acc[3]};
+    double qb[5];
+    prim_vjp(q, gm1, a.R, acc[0], ub, acc[4], Pb, Tb, qb);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] += qb[c] + qdir[c];
+}
+
+template <int N, int EPW, bool OR>
+int launch_vjp_or(const VjpArgs &a, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
     const long long blocks = (a.K + EPW - 1) / EPW;
+    const long long nb = (a.nodes + 255) / 256;
     if (a.mu != 0.0) {
         hipLaunchKernelGGL((k_vjp_visc<N, EPW>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;
-        hipLaunchKernelGGL((k_vjp_main<N, EPW, true>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_main<N, EPW, true, OR>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return -1;
+        hipLaunchKernelGGL((k_vjp_bnd<N, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_vjp_main<N, EPW, false>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_main<N, EPW, false, OR>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return -1;
+        hipLaunchKernelGGL((k_vjp_bnd<N, false>), dim3((unsigned)nb), dim3(256), 0, s, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, int EPW>
+int launch_vjp_n(const VjpArgs &a, hipStream_t s) {
+    return a.orient != nullptr ? launch_vjp_or<N, EPW, true>(a, s) : launch_vjp_or<N, EPW, false>(a, s);
 }
 
 }  // namespace
