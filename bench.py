@@ -68,10 +68,10 @@ def algorithmic_bytes(p, K, viscous):
 # HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
 # this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
 # copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
-TRAFFIC = {"sha256": "c7b2dd07984f55cea05c96a17fc8f940ad98d0c85d6fcafa754193debe9c5b0f",
+TRAFFIC = {"sha256": "17dd44d5d936caae141503898b6432c66aca57b3a57dc339f21b6bbe119d13de",
            "workload": "ns_tgv_p4_e32",
            # bytes per launch by residual schedule index (degree 4)
-           "bytes": {0: 1313437901, 1: 1298575053, 2: 1036515942, 3: 1026041754, 4: 1313026765, 5: 1296691302, 6: 1273823334}}
+           "bytes": {0: 1313845760, 1: 1293187992, 2: 1036720208, 3: 1025975360, 4: 1313513272, 5: 1292876488, 6: 1273874551}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 
@@ -145,7 +145,7 @@ def device_problem(P, W, prob, dev):
     metric, jac = P.metrics(prob.p, coords.reshape(3, -1).contiguous())
     q = W.state(prob, coords).reshape(-1).contiguous()
     dt = W.cfl_dt(prob, coords)
-    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(W.neighbours(prob.E), device=dev),
+    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(W.problem_neighbours(prob), device=dev),
                    metric=metric, jac=jac, gamma=prob.gamma, R=prob.R, mu=prob.mu, Pr=prob.Pr,
                    eta=prob.eta, iface_diss=prob.iface_diss, two_point=prob.two_point)
     return dp, q, dt
@@ -192,6 +192,53 @@ def vjp_rate(P, W, dev, reps):
     return {"Mdof_vjp_per_s": round(prob.n_nodes / (ms_v * 1e-3) / 1e6, 1), "ms": round(ms_v, 4),
             "residual_ms": round(ms_r, 4), "vjp_over_residual_cost": round(ms_v / ms_r, 3),
             "nodes": prob.n_nodes}
+
+
+def mesh_variants_rate(P, W, dev, reps, E=16):
+    """The Taylor-Green problem (p = 4) on E^3 elements with every element turned by a random
+    rotation of the cube (unstructured faces: neighbour face and orientation table), against the
+    same mesh aligned with the default and the autotuned schedule; and the wall-bounded channel
+    (adiabatic no-slip walls on two faces) of the same size."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from workloads import unstructured as U
+    prob = dataclasses.replace(W.config("ns_tgv_p4_e32"), E=E, name=f"ns_tgv_p4_e{E}")
+    out_n = lambda ms: round(prob.n_nodes / (ms * 1e-3) / 1e6, 1)  # noqa: E731
+    x1d, _, _ = P.lgl_operator(prob.p)
+    x = W.coords(prob, x1d).numpy()
+    q0 = W.state(prob, torch.as_tensor(x)).numpy()
+    rots = np.random.Generator(np.random.PCG64(17)).integers(0, 24, prob.K)
+    xr = U.rotate_elements(x, rots)
+    nbr, orient = U.connectivity(xr, prob.L)
+    metric, jac = P.metrics(prob.p, torch.as_tensor(xr.reshape(3, -1), device=dev).contiguous())
+    q = torch.as_tensor(U.rotate_elements(q0, rots).reshape(-1), device=dev).contiguous()
+    dp = P.Problem(p=prob.p, n_elem=prob.K, nbr=torch.as_tensor(nbr, device=dev), metric=metric, jac=jac,
+                   gamma=prob.gamma, R=prob.R, mu=prob.mu, Pr=prob.Pr, eta=prob.eta,
+                   face_orient=torch.as_tensor(orient, device=dev))
+    ps = P.ProblemSet([dp])
+    out = torch.empty_like(q)
+    ms_rot = timed(lambda: ps.residual(q, out), reps)
+    ps.status()
+    dp0, qa, _ = device_problem(P, W, prob, dev)
+    ps0 = P.ProblemSet([dp0])
+    ps0.set_schedule(prob.p, 0)
+    ms_al0 = timed(lambda: ps0.residual(qa, out), reps)
+    ps0.autotune(qa, reps=2)
+    ms_al = timed(lambda: ps0.residual(qa, out), reps)
+    ps0.status()
+    ch = W.channel_problem(prob.p, E, A=0.05)
+    dpc, qc, _ = device_problem(P, W, ch, dev)
+    psc = P.ProblemSet([dpc])
+    psc.autotune(qc, reps=2)
+    ms_ch = timed(lambda: psc.residual(qc, out), reps)
+    psc.status()
+    return {"unstructured": {"Mdof_res_per_s": out_n(ms_rot), "ms": round(ms_rot, 4),
+                             "aligned_default_schedule_ms": round(ms_al0, 4),
+                             "aligned_autotuned_ms": round(ms_al, 4), "nodes": prob.n_nodes,
+                             "orientation_codes": len(set((orient // 8).ravel().tolist()))},
+            "channel_adiabatic_walls": {"Mdof_res_per_s": out_n(ms_ch), "ms": round(ms_ch, 4),
+                                        "nodes": ch.n_nodes}}
 
 
 def batched_rate(P, W, dev, steps, loop_baseline=True):
@@ -267,6 +314,7 @@ def cost_experiment(P, W, dev, steps):
                                    "ms_per_rk4_step": round(ms_rk, 3),
                                    "Mdof_res_per_s": round(prob.n_nodes / (ms_res * 1e-3) / 1e6, 1),
                                    "paper_s_per_dopri5_step_64_haswell_cores": paper[p][name]})
+            print(json.dumps(out["results"][-1]), file=sys.stderr, flush=True)
             del ps, dp, q, out_t
             torch.cuda.empty_cache()
     return out
@@ -569,6 +617,7 @@ def main():
             "vjp_p4_e16": vjp_rate(P, W, dev, 10),
             "batched_256_rk4x10": batched_rate(P, W, dev, 10),
         }
+        extra.update({k + "_p4_e16": v for k, v in mesh_variants_rate(P, W, dev, 10).items()})
 
     cpu = None
     if not args.no_cpu_baseline:

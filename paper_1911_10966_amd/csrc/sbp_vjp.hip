@@ -811,12 +811,8 @@ k_vjp_main(const VjpArgs a) {
 // Kept out of pass 2 so that its registers do not lower that kernel's occupancy.
 // ------------------------------------------------------------------------------------------
 template <int N, bool VISC>
-__global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
+__device__ __forceinline__ void bnd_node(const VjpArgs &a, long long g) {
     constexpr int N2 = N * N, N3 = N * N * N;
-    // nothing to do unless the main pass met a boundary face in this launch
-    if (__hip_atomic_load(a.bnd_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.gen) return;
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.nodes) return;
     const long long e = g / N3;
     const int ln = (int)(g - e * N3);
     const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
@@ -914,11 +910,25 @@ __global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
     for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] += qb[c] + qdir[c];
 }
 
+// A grid of a few blocks per CU walks the nodes: when no boundary face was met, the pass is one
+// load per thread.
+constexpr long long kBndBlocks = 1024;
+
+template <int N, bool VISC>
+__global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
+    // nothing to do unless the main pass met a boundary face in this launch
+    if (__hip_atomic_load(a.bnd_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.gen) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < a.nodes; g += stride)
+        bnd_node<N, VISC>(a, g);
+}
+
 template <int N, int EPW, bool OR>
 int launch_vjp_or(const VjpArgs &a, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
     const long long blocks = (a.K + EPW - 1) / EPW;
-    const long long nb = (a.nodes + 255) / 256;
+    long long nb = (a.nodes + 255) / 256;
+    if (nb > kBndBlocks) nb = kBndBlocks;
     if (a.mu != 0.0) {
         hipLaunchKernelGGL((k_vjp_visc<N, EPW>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;

@@ -101,6 +101,7 @@ DOT = [
     (6, 2, 0.01, (None, -3, None), True, 1),
     (7, 2, 0.0, (-2, None, None), True, 1),
     (8, 2, 0.01, (-3, -1, -3), False, 1),
+    (5, 12, 0.0, (-2, None, -3), False, 1),   # more nodes than one sweep of the boundary pass's grid
 ]
 
 
