@@ -68,10 +68,10 @@ def algorithmic_bytes(p, K, viscous):
 # HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
 # this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
 # copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
-TRAFFIC = {"sha256": "17dd44d5d936caae141503898b6432c66aca57b3a57dc339f21b6bbe119d13de",
+TRAFFIC = {"sha256": "f32098077683836208571f657512c15743e029da53ad064848b5b7bf82fcbf40",
            "workload": "ns_tgv_p4_e32",
            # bytes per launch by residual schedule index (degree 4)
-           "bytes": {0: 1313845760, 1: 1293187992, 2: 1036720208, 3: 1025975360, 4: 1313513272, 5: 1292876488, 6: 1273874551}}
+           "bytes": {0: 1314048216, 1: 1293536824, 2: 1036425728, 3: 1026077112, 4: 1312754008, 5: 1294276504, 6: 1274524949}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 

@@ -106,8 +106,8 @@ int launch_group_rk_stage(int p, bool visc, const GroupArgs &g, const RkGroupArg
 // Degrees whose elements exceed one workgroup (p >= 9) run as passes over node planes; a
 // schedule's `epw` is then the number of planes per workgroup.
 constexpr int kFirstPlaneP = 9;
-int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, const GroupArgs &g,
-                                 hipStream_t s);
+int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, bool orient,
+                                 const GroupArgs &g, hipStream_t s);
 int launch_metrics_big(int p, long long K, const double *x, double *metric, double *jac,
                        const double *D, hipStream_t s);
 

@@ -763,7 +763,7 @@ int launch_group_residual(int p, bool visc, int flux, bool md, bool orient, int 
     if ((flux != 0 || md || orient) && variant != 0) return -1;
     const Schedule sc = schedule_of(p, variant);
     // high degrees: plane passes, which finish SAT^V themselves (no fixup)
-    if (p >= kFirstPlaneP) return launch_group_residual_planes(p, sc.epw, visc, flux, md, g, s);
+    if (p >= kFirstPlaneP) return launch_group_residual_planes(p, sc.epw, visc, flux, md, orient, g, s);
     int rc = -1;
     const bool P1 = sc.persistent != 0;
     if (orient) {

@@ -157,7 +157,7 @@ __device__ __forceinline__ int plane_problem(const GroupArgs &g, long long &vb) 
 }
 
 // ---- pass A: planes of constant xi3 (directions xi1, xi2) -------------------------------------
-template <int N, int PPB, bool VISC, int FLUX, bool MD>
+template <int N, int PPB, bool VISC, int FLUX, bool MD, bool OR>
 __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs g) {
     constexpr int N2 = N * N, N3 = N2 * N, NODES = PPB * N2;
     constexpr int ITEMS = PPB * 4 * N;  // face nodes of the plane: 2 directions x 2 sides x N
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
                 int lp = l;
                 double sg = 1.0;
                 if (kind == FACE_INTERIOR) {
-                    const FaceLink k = face_link<N>(a, e, f, t, j3, lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N));
+                    const FaceLink k = face_link<N, OR>(a, e, f, t, j3, lno + (N - 1 - 2 * il) * (l == 0 ? 1 : N));
                     if (!k.ok) atomicOr(a.status, FLAG_MESH);
                     pg = nb * N3 + k.lno;
                     lp = k.fp >> 1;
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_a(const GroupArgs 
 }
 
 // ---- pass B: planes of constant xi2 (direction xi3) --------------------------------------------
-template <int N, int PPB, bool VISC, int FLUX, bool MD>
+template <int N, int PPB, bool VISC, int FLUX, bool MD, bool OR>
 __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs g) {
     constexpr int N2 = N * N, N3 = N2 * N, NODES = PPB * N2;
     constexpr int ITEMS = PPB * 2 * N;  // face nodes of the plane: 2 sides x N
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(NT_OF(PPB * N * N)) k_plane_b(const GroupArgs 
                 int lp = 2;
                 double sg = 1.0;
                 if (kind == FACE_INTERIOR) {
-                    const FaceLink k = face_link<N>(a, ee, 4 + side, t, j2, lno + (N - 1 - 2 * il) * N2);
+                    const FaceLink k = face_link<N, OR>(a, ee, 4 + side, t, j2, lno + (N - 1 - 2 * il) * N2);
                     if (!k.ok) atomicOr(a.status, FLAG_MESH);
                     pg = nb * N3 + k.lno;
                     lp = k.fp >> 1;
@@ -652,14 +652,14 @@ k_metrics_big(const double *x, double *metric, double *jac, const double *D, lon
     }
 }
 
-template <int N, int PPB, bool VISC, int FLUX, bool MD>
+template <int N, int PPB, bool VISC, int FLUX, bool MD, bool OR = false>
 int launch_planes_k(const GroupArgs &g, hipStream_t s) {
     constexpr int NT = NT_OF(PPB * N * N);
     const dim3 grid((unsigned)g.total_blocks);
     KernelTimer &tm = residual_timer();
     if (tm.enabled && hipEventRecord(tm.begin, s) != hipSuccess) return -1;
-    hipLaunchKernelGGL((k_plane_a<N, PPB, VISC, FLUX, MD>), grid, dim3(NT), 0, s, g);
-    hipLaunchKernelGGL((k_plane_b<N, PPB, VISC, FLUX, MD>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_plane_a<N, PPB, VISC, FLUX, MD, OR>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_plane_b<N, PPB, VISC, FLUX, MD, OR>), grid, dim3(NT), 0, s, g);
     if constexpr (VISC) hipLaunchKernelGGL((k_plane_c<N, PPB>), grid, dim3(NT), 0, s, g);
     if (hipGetLastError() != hipSuccess) return -1;
     if (tm.enabled && hipEventRecord(tm.end, s) != hipSuccess) return -1;
@@ -687,24 +687,45 @@ int launch_planes_md(bool visc, int flux, const GroupArgs &g, hipStream_t s) {
     }
 }
 
+// Problems with a face-orientation table: one plane per workgroup, every flux and dissipation.
 template <int N>
-int launch_planes_n(int ppb, bool visc, int flux, bool md, const GroupArgs &g, hipStream_t s) {
+int launch_planes_or(bool visc, int flux, bool md, const GroupArgs &g, hipStream_t s) {
+    if (md) {
+        switch (flux) {
+            case 0: return visc ? launch_planes_k<N, 1, true, 0, true, true>(g, s) : launch_planes_k<N, 1, false, 0, true, true>(g, s);
+            case 2: return visc ? launch_planes_k<N, 1, true, 2, true, true>(g, s) : launch_planes_k<N, 1, false, 2, true, true>(g, s);
+            default: return -1;
+        }
+    }
+    switch (flux) {
+        case 0: return visc ? launch_planes_k<N, 1, true, 0, false, true>(g, s) : launch_planes_k<N, 1, false, 0, false, true>(g, s);
+        case 1: return visc ? launch_planes_k<N, 1, true, 1, false, true>(g, s) : launch_planes_k<N, 1, false, 1, false, true>(g, s);
+        case 2: return visc ? launch_planes_k<N, 1, true, 2, false, true>(g, s) : launch_planes_k<N, 1, false, 2, false, true>(g, s);
+        case 3: return visc ? launch_planes_k<N, 1, true, 3, false, true>(g, s) : launch_planes_k<N, 1, false, 3, false, true>(g, s);
+        default: return -1;
+    }
+}
+
+template <int N>
+int launch_planes_n(int ppb, bool visc, int flux, bool md, bool orient, const GroupArgs &g,
+                    hipStream_t s) {
+    if (orient) return ppb == 1 ? launch_planes_or<N>(visc, flux, md, g, s) : -1;
     if (md) return ppb == 1 ? launch_planes_md<N>(visc, flux, g, s) : -1;
     return ppb == 2 ? launch_planes_f<N, 2>(visc, flux, g, s) : launch_planes_f<N, 1>(visc, flux, g, s);
 }
 
 }  // namespace
 
-int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, const GroupArgs &g,
-                                 hipStream_t s) {
+int launch_group_residual_planes(int p, int ppb, bool visc, int flux, bool md, bool orient,
+                                 const GroupArgs &g, hipStream_t s) {
     switch (p) {
-        case 9: return launch_planes_n<10>(ppb, visc, flux, md, g, s);
-        case 10: return launch_planes_n<11>(ppb, visc, flux, md, g, s);
-        case 11: return launch_planes_n<12>(ppb, visc, flux, md, g, s);
-        case 12: return launch_planes_n<13>(ppb, visc, flux, md, g, s);
-        case 13: return launch_planes_n<14>(ppb, visc, flux, md, g, s);
-        case 14: return launch_planes_n<15>(ppb, visc, flux, md, g, s);
-        case 15: return launch_planes_n<16>(ppb, visc, flux, md, g, s);
+        case 9: return launch_planes_n<10>(ppb, visc, flux, md, orient, g, s);
+        case 10: return launch_planes_n<11>(ppb, visc, flux, md, orient, g, s);
+        case 11: return launch_planes_n<12>(ppb, visc, flux, md, orient, g, s);
+        case 12: return launch_planes_n<13>(ppb, visc, flux, md, orient, g, s);
+        case 13: return launch_planes_n<14>(ppb, visc, flux, md, orient, g, s);
+        case 14: return launch_planes_n<15>(ppb, visc, flux, md, orient, g, s);
+        case 15: return launch_planes_n<16>(ppb, visc, flux, md, orient, g, s);
         default: return -1;
     }
 }
