@@ -548,7 +548,8 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
         return SBP_ERR_ARG;
     for (int b = 0; b < n_prob; ++b) {
-        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR || probs[b].iface_diss == 2)
+        if ((probs[b].two_point != SBP_FLUX_CHANDRASHEKAR &&
+             probs[b].two_point != SBP_FLUX_KENNEDY_GRUBER) || probs[b].iface_diss == 2)
             return SBP_ERR_ARG;
         if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
     }
@@ -581,6 +582,7 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
         a.eta = pr.eta;
         a.w_end = host_op(pr.p).w[0];
         a.iface_diss = pr.iface_diss;
+        a.two_point = pr.two_point;
         if (sbp::launch_vjp(pr.p, a, (hipStream_t)stream) != 0) return SBP_ERR_HIP;
         off += 5 * (size_t)nodes_of(pr);
     }

@@ -134,6 +134,49 @@ __device__ __forceinline__ void flux_n_vjp(const Node &a, const Node &b, double 
     ab.k = bb.k = 0.5 * kbb;
 }
 
+// Reverse of flux_n<2> (Kennedy-Gruber split form contracted with a constant vector n): with
+// P = rho/(2 beta) and E = P/((gamma-1) rho) + |U|^2/2 = 1/(2 (gamma-1) beta) + |U|^2/2 per node,
+// f = rho_bar U_bar.n [1, U_bar, E_bar] + P_bar [0, n, U_bar.n] (bars: arithmetic means).
+__device__ __forceinline__ void kg_flux_n_vjp(const Node &a, const Node &b, double n0, double n1,
+                                              double n2, double gm1, const double fb[5], NodeBar &ab,
+                                              NodeBar &bb) {
+    const double ub1 = 0.5 * (a.u1 + b.u1), ub2 = 0.5 * (a.u2 + b.u2), ub3 = 0.5 * (a.u3 + b.u3);
+    const double un = ub1 * n0 + ub2 * n1 + ub3 * n2;
+    const double rbar = 0.5 * (a.rho + b.rho);
+    const double iba = 1.0 / a.beta, ibb = 1.0 / b.beta;
+    const double Pbar = 0.25 * (a.rho * iba + b.rho * ibb);
+    const double c = 0.5 / gm1;
+    const double Ebar = 0.5 * (c * iba + 0.5 * a.k + c * ibb + 0.5 * b.k);
+    const double fr = rbar * un;
+    // reverse sweep
+    const double frb = fb[0] + fb[1] * ub1 + fb[2] * ub2 + fb[3] * ub3 + fb[4] * Ebar;
+    const double Ebarb = fb[4] * fr;
+    const double Pbarb = fb[1] * n0 + fb[2] * n1 + fb[3] * n2 + fb[4] * un;
+    const double unb = frb * rbar + fb[4] * Pbar;
+    const double rbarb = frb * un;
+    const double u1b = fb[1] * fr + unb * n0, u2b = fb[2] * fr + unb * n1, u3b = fb[3] * fr + unb * n2;
+    // Pbar = (rho_a/beta_a + rho_b/beta_b)/4, Ebar = (c/beta_a + k_a/2 + c/beta_b + k_b/2)/2
+    ab.rho = 0.5 * rbarb + 0.25 * Pbarb * iba;
+    bb.rho = 0.5 * rbarb + 0.25 * Pbarb * ibb;
+    ab.beta = -(0.25 * Pbarb * a.rho + 0.5 * Ebarb * c) * iba * iba;
+    bb.beta = -(0.25 * Pbarb * b.rho + 0.5 * Ebarb * c) * ibb * ibb;
+    ab.lrho = bb.lrho = 0.0;
+    ab.lbeta = bb.lbeta = 0.0;
+    ab.u1 = bb.u1 = 0.5 * u1b;
+    ab.u2 = bb.u2 = 0.5 * u2b;
+    ab.u3 = bb.u3 = 0.5 * u3b;
+    ab.k = bb.k = 0.25 * Ebarb;
+}
+
+// Reverse of the two-point flux of the volume form FLUX (0 Chandrashekar, 2 Kennedy-Gruber).
+template <int FLUX, bool LAZY = false>
+__device__ __forceinline__ void two_point_vjp(const Node &a, const Node &b, double n0, double n1,
+                                              double n2, double gm1, const double fb[5], NodeBar &ab,
+                                              NodeBar &bb) {
+    if constexpr (FLUX == 2) kg_flux_n_vjp(a, b, n0, n1, n2, gm1, fb, ab, bb);
+    else flux_n_vjp<LAZY>(a, b, n0, n1, n2, gm1, fb, ab, bb);
+}
+
 // Folds the cotangents of log rho, log beta and |U|^2 into (rho, U, beta) of the same node.
 __device__ __forceinline__ void reduce_bar(const Node &n, const NodeBar &z, double out[5]) {
     out[0] = z.rho + z.lrho / n.rho;
@@ -435,7 +478,7 @@ k_vjp_visc(const VjpArgs a) {
 // momentum reversed or reflected, differentiated through the own state).  Accumulates the
 // cotangents of the own node's (rho, U, beta) in acc, of P and T, of q directly (qdir), and of the
 // entropy variables (wb).
-template <bool VISC, bool BND>
+template <bool VISC, bool BND, int FLUX>
 __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, const double q[5],
                                               const double rb[5], const double Al[3], double iJ,
                                               double Pme, double Tme, const double wme[4], double s,
@@ -455,7 +498,7 @@ __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, 
 #pragma unroll
     for (int c = 0; c < 5; ++c) fb[c] = -s * isw * (rb[c] - rbn[c]);
     NodeBar ab, bb;
-    flux_n_vjp<true>(me, o, n0, n1, n2, gm1, fb, ab, bb);
+    two_point_vjp<FLUX, true>(me, o, n0, n1, n2, gm1, fb, ab, bb);
     double ra[5];
     reduce_bar(me, ab, ra);
 #pragma unroll
@@ -562,7 +605,7 @@ __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, 
 // ------------------------------------------------------------------------------------------
 // Pass 2: everything else; adds to the partial qbar of pass 1 when VISC.
 // ------------------------------------------------------------------------------------------
-template <int N, int EPW, bool VISC, bool OR>
+template <int N, int EPW, bool VISC, bool OR, int FLUX>
 __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
 __attribute__((amdgpu_waves_per_eu(OR ? 2 : 1, 8)))  // the orientation lookup would cost a wave
 k_vjp_main(const VjpArgs a) {
@@ -657,7 +700,7 @@ k_vjp_main(const VjpArgs a) {
 #pragma unroll
             for (int c = 0; c < 5; ++c) fb[c] = -dab * rb[c] - dba * s_buf[(F_RB + c) * NODES + pn];
             NodeBar ab, bb;
-            flux_n_vjp(me, o, n0, n1, n2, gm1, fb, ab, bb);
+            two_point_vjp<FLUX>(me, o, n0, n1, n2, gm1, fb, ab, bb);
             double ra[5];
             reduce_bar(me, ab, ra);
 #pragma unroll
@@ -734,7 +777,7 @@ k_vjp_main(const VjpArgs a) {
                 qn[c] = a.q[c * nodes + pg];
                 rbn[c] = a.gbar[c * nodes + pg] * iJn;
             }
-            face_term_vjp<VISC, false>(a, me, q, rb, A[l], iJ, Pme, Tme, wme, s, kind, qn, rbn, An, iJn,
+            face_term_vjp<VISC, false, FLUX>(a, me, q, rb, A[l], iJ, Pme, Tme, wme, s, kind, qn, rbn, An, iJn,
                                        acc, Pb, Tb, qdir, wb);
         }
     }
@@ -810,7 +853,7 @@ k_vjp_main(const VjpArgs a) {
 // Pass 3: boundary faces (Dirichlet, slip and no-slip walls), one thread per node; adds to qbar.
 // Kept out of pass 2 so that its registers do not lower that kernel's occupancy.
 // ------------------------------------------------------------------------------------------
-template <int N, bool VISC>
+template <int N, bool VISC, int FLUX>
 __device__ __forceinline__ void bnd_node(const VjpArgs &a, long long g) {
     constexpr int N2 = N * N, N3 = N * N * N;
     const long long e = g / N3;
@@ -879,7 +922,7 @@ __device__ __forceinline__ void bnd_node(const VjpArgs &a, long long g) {
                 for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, Al[m], q[1 + m]);
             }
         }
-        face_term_vjp<VISC, true>(a, me, q, rb, Al, iJ, Pme, Tme, wme, s, kind, qn, zero, Al, iJ, acc, Pb,
+        face_term_vjp<VISC, true, FLUX>(a, me, q, rb, Al, iJ, Pme, Tme, wme, s, kind, qn, zero, Al, iJ, acc, Pb,
                                   Tb, qdir, wb);
         if constexpr (VISC) {
             // transposed SAT^theta of the boundary face: (s/(2 w_end)) (w_ghost - w_i)
@@ -914,17 +957,17 @@ __device__ __forceinline__ void bnd_node(const VjpArgs &a, long long g) {
 // load per thread.
 constexpr long long kBndBlocks = 1024;
 
-template <int N, bool VISC>
+template <int N, bool VISC, int FLUX>
 __global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
     // nothing to do unless the main pass met a boundary face in this launch
     if (__hip_atomic_load(a.bnd_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.gen) return;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < a.nodes; g += stride)
-        bnd_node<N, VISC>(a, g);
+        bnd_node<N, VISC, FLUX>(a, g);
 }
 
-template <int N, int EPW, bool OR>
-int launch_vjp_or(const VjpArgs &a, hipStream_t s) {
+template <int N, int EPW, bool OR, int FLUX>
+int launch_vjp_f(const VjpArgs &a, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
     const long long blocks = (a.K + EPW - 1) / EPW;
     long long nb = (a.nodes + 255) / 256;
@@ -932,15 +975,24 @@ int launch_vjp_or(const VjpArgs &a, hipStream_t s) {
     if (a.mu != 0.0) {
         hipLaunchKernelGGL((k_vjp_visc<N, EPW>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;
-        hipLaunchKernelGGL((k_vjp_main<N, EPW, true, OR>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_main<N, EPW, true, OR, FLUX>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;
-        hipLaunchKernelGGL((k_vjp_bnd<N, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_bnd<N, true, FLUX>), dim3((unsigned)nb), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_vjp_main<N, EPW, false, OR>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_main<N, EPW, false, OR, FLUX>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;
-        hipLaunchKernelGGL((k_vjp_bnd<N, false>), dim3((unsigned)nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_bnd<N, false, FLUX>), dim3((unsigned)nb), dim3(256), 0, s, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, int EPW, bool OR>
+int launch_vjp_or(const VjpArgs &a, hipStream_t s) {
+    switch (a.two_point) {
+        case 0: return launch_vjp_f<N, EPW, OR, 0>(a, s);
+        case 2: return launch_vjp_f<N, EPW, OR, 2>(a, s);
+        default: return -1;
+    }
 }
 
 template <int N, int EPW>

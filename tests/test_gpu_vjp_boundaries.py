@@ -1,7 +1,8 @@
-"""Hand-written VJP with boundary faces (Dirichlet, slip wall, adiabatic no-slip wall) and on
-unstructured meshes (face-orientation table), against the oracle: the extended-precision
-complex-step Jacobian on small meshes, the dot-product identity gbar.(J v) = qbar.v with the
-oracle's complex-step J v for p up to 8, and central differences of the GPU residual."""
+"""Hand-written VJP with boundary faces (Dirichlet, slip wall, adiabatic no-slip wall), on
+unstructured meshes (face-orientation table) and with the Kennedy-Gruber (SF-KG) volume form,
+against the oracle: the extended-precision complex-step Jacobian on small meshes, the dot-product
+identity gbar.(J v) = qbar.v with the oracle's complex-step J v for p up to 8, and central
+differences of the GPU residual."""
 import numpy as np
 import pytest
 import torch
@@ -21,9 +22,9 @@ class BCase:
     """A problem with boundary kinds per box direction, or with every element turned by a random
     rotation of the cube (face table from the coordinates)."""
 
-    def __init__(self, p, E, mu, box=(None, None, None), rotate=False, seed=1, diss=1, eta=1.0):
+    def __init__(self, p, E, mu, box=(None, None, None), rotate=False, seed=1, diss=1, eta=1.0, tp=0):
         prob = W.make_problem(p=p, E=E, L=2.0, A=0.1, mu=mu, iface_diss=diss, eta=eta, seed=seed,
-                              u_rms=0.3, box=box)
+                              u_rms=0.3, box=box, two_point=tp)
         c = Case(prob)
         self.prob, self.sbp, self.prm = prob, c.sbp, c.prm
         self.q = c.jumpy(0.02, seed + 1)
@@ -119,6 +120,40 @@ def test_boundary_vjp_dot_product_with_complex_step_jvp(p, E, mu, box, rotate, d
     scale = np.abs(gb * jv).sum()
     print(f"  dot: rel {abs(lhs - rhs) / scale:.2e}")
     assert abs(lhs - rhs) < TOL * scale
+
+
+KG = [
+    # p, E, mu, box, rotate: the Kennedy-Gruber volume form
+    (1, 2, 0.02, (-3, None, None), False),
+    (2, 2, 0.0, (None, None, None), True),
+]
+
+
+@pytest.mark.parametrize("p,E,mu,box,rotate", KG)
+def test_kennedy_gruber_vjp_matches_full_jacobian(p, E, mu, box, rotate):
+    require_gpu()
+    print(f"kg vjp full jacobian p={p} E={E} mu={mu} box={box} rotate={rotate}", flush=True)
+    c = BCase(p, E, mu, box, rotate, seed=20 + p, tp=2)
+    LD = np.longdouble
+    Jm = jvp.full_jacobian(c.q, c.metric.astype(LD), c.jac.astype(LD), c.nbr, operators.SBP1D(p, LD),
+                           c.prm, ctype=np.clongdouble, **c.kw())
+    gb = np.random.Generator(np.random.PCG64(4)).standard_normal(c.q.shape)
+    ref = (Jm.T @ gb.ravel().astype(LD)).reshape(c.q.shape).astype(np.float64)
+    err = rel_err(c.vjp(c.q, gb), ref)
+    print(f"  gpu vs extended-precision J^T gbar: {err:.2e}")
+    assert err < TOL
+
+
+@pytest.mark.parametrize("p,E,mu,box", [(4, 2, 0.01, (None, -3, None)), (7, 2, 0.0, (None, None, None))])
+def test_kennedy_gruber_vjp_dot_product(p, E, mu, box):
+    require_gpu()
+    c = BCase(p, E, mu, box, False, seed=30 + p, tp=2)
+    gb = np.random.Generator(np.random.PCG64(p)).standard_normal(c.q.shape)
+    v = W.direction(torch.as_tensor(c.q), 5).numpy()
+    jv = jvp.jvp(c.q, v, c.metric, c.jac, c.nbr, c.sbp, c.prm, **c.kw())
+    qb = c.vjp(c.q, gb)
+    lhs, rhs = (gb * jv).sum(), (qb * v).sum()
+    assert abs(lhs - rhs) < TOL * np.abs(gb * jv).sum()
 
 
 def test_boundary_vjp_central_difference():
