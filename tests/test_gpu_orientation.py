@@ -137,3 +137,29 @@ def test_invalid_orientation_entry_is_a_mesh_error():
     ps.residual(to_dev(c.q))
     with pytest.raises(P.SBPError):
         ps.status()
+
+
+def test_batch_of_rotated_and_aligned_problems():
+    """A rotated and an aligned problem of the same degree in one set (two launch groups), one
+    residual and one RK4 step, each against its own oracle."""
+    require_gpu()
+    from helpers import Case
+    from gpu_helpers import device_problem
+    pr = W.make_problem(p=3, E=2, L=2.0, A=0.1, mu=0.01, seed=5, u_rms=0.3)
+    cr = RotCase(pr, seed=9)
+    ca = Case(W.make_problem(p=3, E=2, L=2.0, A=0.1, mu=0.01, seed=6, u_rms=0.3))
+    ps = P.ProblemSet([cr.device(), device_problem(ca)])
+    qa = ca.jumpy(0.01, 2)
+    q = torch.cat([to_dev(cr.q), to_dev(qa)])
+    out = ps.residual(q).cpu().numpy()
+    assert ps.status() == 0
+    n = cr.q.size
+    ref_r = R.residual(cr.q, cr.metric, cr.jac, cr.nbr, cr.sbp, cr.prm, orient=cr.orient)
+    assert rel_err(out[:n].reshape(cr.q.shape), ref_r) < _tol(cr, ref_r)
+    assert rel_err(out[n:].reshape(qa.shape), ca.residual(qa)) < 1e-12
+    ps.rk_step(q, torch.tensor([2e-3, 2e-3], dtype=torch.float64, device=DEV), 1)
+    assert ps.status() == 0
+    q1 = q.cpu().numpy()
+    f = lambda y: R.residual(y, cr.metric, cr.jac, cr.nbr, cr.sbp, cr.prm, orient=cr.orient)  # noqa: E731
+    assert rel_err(q1[:n].reshape(cr.q.shape) - cr.q, R.rk4_step(f, cr.q, 2e-3) - cr.q) < 1e-10
+    assert rel_err(q1[n:].reshape(qa.shape) - qa, R.rk4_step(ca.residual, qa, 2e-3) - qa) < 1e-10
