@@ -17,8 +17,9 @@
  *   The residual is entropy conservative only when the metrics satisfy the discrete geometric
  *   conservation law (eq. discGCLconvection); sbp_metrics() produces such metrics (curl form).
  * - nbr: [K][6] int32, face f = 2*l + s (s = 0 for the xi_l = -1 face, 1 for xi_l = +1) of element e
- *   touches element nbr[e*6 + f]; faces are conforming and aligned (the neighbour's opposite face,
- *   same tangential node indices).  Periodic grids list wrap-around neighbours.  A negative entry
+ *   touches element nbr[e*6 + f]; faces are conforming, and aligned (the neighbour's opposite face,
+ *   same tangential node indices) unless the problem carries a face_orient table (unstructured
+ *   meshes, below).  Periodic grids list wrap-around neighbours.  A negative entry
  *   makes the face a boundary face of the kind it names (SBP_BC_*, below); any other entry outside
  *   [0, K) is a mesh error (sticky flag, SBP_ERR_MESH from sbp_status()).
  * - Pointers marked "device" are HIP device allocations owned by the caller; the library never
@@ -58,9 +59,9 @@ extern "C" {
 #define SBP_FLUX_DC 3            /* standard DC: SBP derivative of the nodal fluxes, central   */
                                  /* interface flux                                             */
 
-/* One periodic problem.  Constants follow the constituent relations of the compressible
- * Navier-Stokes section: P = rho R T, c_p = gamma R / (gamma - 1), constant viscosity mu and
- * conductivity kappa = mu c_p / Pr; mu == 0 evaluates the Euler residual only. */
+/* One problem: a mesh of K elements of degree p.  Constants follow the constituent relations of
+ * the compressible Navier-Stokes section: P = rho R T, c_p = gamma R / (gamma - 1), constant
+ * viscosity mu and conductivity kappa = mu c_p / Pr; mu == 0 evaluates the Euler residual only. */
 typedef struct sbp_problem {
     int32_t p;              /* polynomial degree, 1..SBP_MAX_P                                 */
     int32_t iface_diss;     /* interface dissipation: 0 none (entropy conservative), 1 local   */
