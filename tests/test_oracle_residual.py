@@ -11,6 +11,7 @@ import torch
 import workloads as W
 from helpers import Case, rel_err
 from oracle import dense, gas as G, jvp, operators, residual as R
+from oracle.geometry import apply_D
 
 
 def face_sum(c, q, fn):
@@ -124,7 +125,6 @@ def test_central_flux_reduces_to_split_form(A):
     q = c.jumpy(0.02, 5)
     V = R.volume_term(q, c.metric, c.sbp, c.prm)
     F = G.euler_flux(q, c.prm.gas)
-    from oracle.geometry import apply_D
     ref = 0
     for l in range(3):
         Al = c.metric[3 * l:3 * l + 3]
@@ -134,6 +134,67 @@ def test_central_flux_reduces_to_split_form(A):
     if A == 0.0:
         ref2 = sum(apply_D(c.sbp.D, G.contract(F, c.metric[3 * l:3 * l + 3]), l) for l in range(3))
         assert rel_err(V, ref2) < 1e-12
+
+
+# ------------------------------------------------------------------ Kennedy-Gruber form (SF-KG)
+def _quad(D, a, b, l):
+    """sum_j 2 D_ij abar_ij bbar_ij along xi_l, written as the quadratic split derivative
+    (a D b + b D a + D(ab)) / 2."""
+    return 0.5 * (a * apply_D(D, b, l) + b * apply_D(D, a, l) + apply_D(D, a * b, l))
+
+
+def _cubic(D, a, b, c, l):
+    """sum_j 2 D_ij abar bbar cbar along xi_l, written as the cubic split derivative of Kennedy and
+    Gruber: [D(abc) + a D(bc) + b D(ac) + c D(ab) + bc D a + ac D b + ab D c] / 4."""
+    d = lambda f: apply_D(D, f, l)  # noqa: E731
+    return 0.25 * (d(a * b * c) + a * d(b * c) + b * d(a * c) + c * d(a * b)
+                   + b * c * d(a) + a * c * d(b) + a * b * d(c))
+
+
+def test_kennedy_gruber_volume_is_the_split_derivative_form():
+    """On an affine mesh, flux differencing with the product-of-averages flux equals the split
+    derivative form of Kennedy and Gruber term by term (the SF-KG form of the comparison)."""
+    c = Case(W.make_problem(p=3, E=2, L=2.0, A=0.0, seed=15, u_rms=0.3, two_point=2))
+    q = c.jumpy(0.03, 11)
+    V = R.volume_term(q, c.metric, c.sbp, c.prm)
+    rho, u, P, _ = G.primitives(q, c.prm.gas)
+    e = q[4] / rho
+    D = c.sbp.D
+    ref = np.zeros_like(q)
+    for l in range(3):
+        for m in range(3):
+            F = [_quad(D, rho, u[m], l)]
+            F += [_cubic(D, rho, u[m], u[k], l) + (apply_D(D, P, l) if k == m else 0.0) for k in range(3)]
+            F += [_cubic(D, rho, u[m], e, l) + _quad(D, P, u[m], l)]
+            ref += c.metric[3 * l + m] * np.stack(F)
+    assert rel_err(V, ref) < 1e-12
+    # the central flux is not this form (the test can tell them apart)
+    Vc = R.volume_term(q, c.metric, c.sbp, R.Params(two_point=1))
+    assert rel_err(Vc, ref) > 1e-4
+
+
+@pytest.mark.parametrize("two_point,preserves", [(2, True), (0, True), (1, False)])
+def test_kinetic_energy_conserved_at_uniform_pressure(two_point, preserves):
+    """Kinetic-energy-preserving two-point fluxes (momentum flux = mass flux times the mean velocity
+    plus a mean pressure) leave the total discrete kinetic energy unchanged on a periodic curvilinear
+    mesh without interface dissipation when the pressure is uniform: the convective part cancels by
+    skew-symmetry and the pressure part by the discrete GCL. Both SF-KG and ES-C are of this kind;
+    the central flux is not."""
+    c = Case(W.make_problem(p=4, E=2, L=2.0, A=0.12, mu=0.0, iface_diss=0, seed=16, u_rms=0.3,
+                            two_point=two_point))
+    q = c.jumpy(0.05, 12)
+    gas = c.prm.gas
+    rho, u = q[0], q[1:4] / q[0]
+    q[4] = 1.0 / (gas.gamma - 1.0) + 0.5 * rho * (u * u).sum(0)
+    r = c.residual(q)
+    wj = c.weights3d() * c.jac
+    ke = (u * r[1:4]).sum(0) - 0.5 * (u * u).sum(0) * r[0]
+    mag = (wj * np.abs(u * r[1:4]).sum(0)).sum()
+    rel = abs((wj * ke).sum()) / mag
+    if preserves:
+        assert rel < 1e-13
+    else:
+        assert rel > 1e-6
 
 
 # ------------------------------------------------------------------ subsets, chunks, precision
