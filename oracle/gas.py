@@ -174,20 +174,22 @@ def matrix_dissipation_operator(qi, qn, nbar, gas: Gas):
     nn = np.sqrt((nbar * nbar).sum(0))
     n = nbar / nn
     vn = (ub * n).sum(0)
+    # |x| continued analytically (sign of the real part), so that the complex step differentiates it
+    cabs = lambda x: np.where(np.real(x) >= 0, x, -x)  # noqa: E731
     one, zero = np.ones_like(vn), np.zeros_like(vn)
     M = np.zeros((5, 5) + vn.shape, dtype=np.result_type(vn, np.float64))
     for sgn in (-1.0, 1.0):
         r = np.stack([one, ub[0] + sgn * a_hat * n[0], ub[1] + sgn * a_hat * n[1],
                       ub[2] + sgn * a_hat * n[2], h_hat + sgn * a_hat * vn])
-        M = M + (np.abs(vn + sgn * a_hat) * rho_hat / (2.0 * g * R)) * r[:, None] * r[None, :]
+        M = M + (cabs(vn + sgn * a_hat) * rho_hat / (2.0 * g * R)) * r[:, None] * r[None, :]
     r = np.stack([one, ub[0], ub[1], ub[2], 0.5 * ubsq])
-    M = M + (np.abs(vn) * rho_hat * (g - 1.0) / (g * R)) * r[:, None] * r[None, :]
+    M = M + (cabs(vn) * rho_hat * (g - 1.0) / (g * R)) * r[:, None] * r[None, :]
     B = np.zeros((3, 5) + vn.shape, dtype=M.dtype)
     for k in range(3):
         B[k, k + 1] = one
         B[k, 4] = ub[k]
     P = np.stack([np.stack([(1.0 if i == j else 0.0) - n[i] * n[j] for j in range(3)]) for i in range(3)])
-    M = M + (np.abs(vn) * p_hat / R) * np.einsum("ka...,kl...,lb...->ab...", B, P, B)
+    M = M + (cabs(vn) * p_hat / R) * np.einsum("ka...,kl...,lb...->ab...", B, P, B)
     return nn * M
 
 

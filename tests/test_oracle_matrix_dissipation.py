@@ -99,3 +99,34 @@ def test_entropy_budget_with_matrix_dissipation():
     rhs = face_sum(c, q, diss)
     assert rhs < 0
     assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+
+
+def test_dissipation_is_odd_in_the_states_and_even_in_the_normal():
+    """M(q_i, q_nu, n) = -M(q_nu, q_i, n) = M(q_i, q_nu, -n): the two sides of a face carry
+    opposite terms, whatever the sign of the normal each side sees."""
+    rng = np.random.default_rng(12)
+    qi, qn = _state(rng, 40), _state(rng, 40)
+    nbar = rng.normal(size=(3, 40))
+    M = G.matrix_dissipation(qi, qn, nbar, GAS)
+    assert np.abs(M + G.matrix_dissipation(qn, qi, nbar, GAS)).max() < 1e-13 * np.abs(M).max()
+    assert np.abs(M - G.matrix_dissipation(qi, qn, -nbar, GAS)).max() < 1e-13 * np.abs(M).max()
+
+
+def test_complex_step_of_the_dissipation_matches_central_differences():
+    """The complex step through the dissipation (|.| continued by the sign of the real part, log
+    means, square roots) gives the same directional derivative as central differences."""
+    rng = np.random.default_rng(13)
+    qi, qn = _state(rng, 30), _state(rng, 30)
+    nbar = rng.normal(size=(3, 30))
+    for side in (0, 1):
+        v = rng.normal(size=qi.shape) * np.array([0.1, 0.1, 0.1, 0.1, 0.5])[:, None]
+        h = 1e-30
+        args = [qi.astype(np.complex128), qn.astype(np.complex128)]
+        args[side] = args[side] + 1j * h * v
+        cs = np.imag(G.matrix_dissipation(*args, nbar, GAS)) / h
+        e = 1e-6
+        ap, am = [qi, qn], [qi, qn]
+        ap[side] = ap[side] + e * v
+        am[side] = am[side] - e * v
+        fd = (G.matrix_dissipation(*ap, nbar, GAS) - G.matrix_dissipation(*am, nbar, GAS)) / (2 * e)
+        assert np.abs(cs - fd).max() < 1e-7 * np.abs(cs).max()
