@@ -178,9 +178,14 @@ def plain_rate(P, W, name, dev, reps):
             "nodes": prob.n_nodes, "p": prob.p}
 
 
-def vjp_rate(P, W, dev, reps):
+def vjp_rate(P, W, dev, reps, iface_diss=None):
+    """VJP and residual of the adjoint workload (p = 4, 16^3 elements); ``iface_diss`` replaces
+    its interface dissipation (2: matrix dissipation)."""
+    import dataclasses
     import torch
     prob = W.config("vjp_p4_e16")
+    if iface_diss is not None:
+        prob = dataclasses.replace(prob, iface_diss=iface_diss)
     dp, q, _ = device_problem(P, W, prob, dev)
     ps = P.ProblemSet([dp])
     ps.autotune(q, reps=2)
@@ -615,6 +620,7 @@ def main():
             "plain_ns_tgv_p4_e32": plain_rate(P, W, "ns_tgv_p4_e32", dev, 10),
             "plain_ns_p7_e16": plain_rate(P, W, "ns_p7_e16", dev, 10),
             "vjp_p4_e16": vjp_rate(P, W, dev, 10),
+            "vjp_matrix_dissipation_p4_e16": vjp_rate(P, W, dev, 10, iface_diss=2),
             "batched_256_rk4x10": batched_rate(P, W, dev, 10),
         }
         extra.update({k + "_p4_e16": v for k, v in mesh_variants_rate(P, W, dev, 10).items()})

@@ -10,6 +10,8 @@
 //   k_vjp_main   the inviscid volume and interface terms, the interior penalty, the transposed
 //                gradient operator with its SAT (reading neighbour theta cotangents), and the map
 //                from primitive cotangents to qbar.
+// Two passes add to qbar afterwards: k_vjp_bnd the boundary faces, and k_vjp_md the matrix
+// interface dissipation (iface_diss = 2), whose derivative is taken in forward mode.
 // Pair terms of the flux-differencing sum use the same cyclic pairing and LDS mailbox as the
 // forward kernel; cotangents are accumulated on the node quantities (rho, U, beta) and mapped to
 // conservative variables once per node.
@@ -519,7 +521,7 @@ __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, 
             for (int m = 0; m < 3; ++m) acc[1 + m] += rg[1 + m] - 2.0 * un * An[m];
         }
     }
-    if (a.iface_diss) {
+    if (a.iface_diss == 1) {  // Lax-Friedrichs; the matrix dissipation has a pass of its own
         const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
         const double unm = me.u1 * n0 + me.u2 * n1 + me.u3 * n2;
         const double cme = sqrt(a.gamma * Pme / me.rho);
@@ -966,6 +968,123 @@ __global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
         bnd_node<N, VISC, FLUX>(a, g);
 }
 
+// ------------------------------------------------------------------------------------------
+// Pass 4 (iface_diss = 2): the matrix interface dissipation, one thread per node; adds to qbar.
+// Across an interior face the two sides' terms are -M(q_i, q_nu)/(2 w_end) and its negative (M is
+// odd in the exchange of the states and even in the sign of the normal), so the own node's
+// cotangent is (dM/dq_i)^T applied to -(rbar_i - rbar_nu)/(2 w_end).  A boundary ghost has no
+// cotangent of its own; a wall ghost is an image of the own state and is differentiated with it.
+// dM/dq_i is taken in forward mode, one own-state component at a time (five evaluations of M).
+// ------------------------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ NodeT<T> md_node(const T q[5], double gm1) {
+    NodeT<T> n;
+    n.rho = q[0];
+    const T ir = rcp(q[0]);
+    n.u1 = q[1] * ir;
+    n.u2 = q[2] * ir;
+    n.u3 = q[3] * ir;
+    n.k = n.u1 * n.u1 + n.u2 * n.u2 + n.u3 * n.u3;
+    const T P = gm1 * (q[4] - 0.5 * q[0] * n.k);
+    n.beta = 0.5 * q[0] * rcp(P);
+    n.lrho = log(q[0]);
+    n.lbeta = log(n.beta);
+    return n;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_vjp_md(const VjpArgs a) {
+    using ad::Dual;
+    constexpr int N2 = N * N, N3 = N * N * N;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nodes) return;
+    const long long e = g / N3;
+    const int ln = (int)(g - e * N3);
+    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+    if (i1 != 0 && i1 != N - 1 && i2 != 0 && i2 != N - 1 && i3 != 0 && i3 != N - 1) return;
+    const long long nodes = a.nodes;
+    const double gm1 = a.gamma - 1.0;
+    const double isw = 1.0 / a.w_end;
+    double q[5], rb[5], qb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double iJ = rcp(a.jac[g]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        q[c] = a.q[c * nodes + g];
+        rb[c] = a.gbar[c * nodes + g] * iJ;
+    }
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        // (selects rather than indexed arrays: the loop is not unrolled)
+        const int il = l == 0 ? i1 : (l == 1 ? i2 : i3);
+        const int st = l == 0 ? 1 : (l == 1 ? N : N2);
+        if (il != 0 && il != N - 1) continue;
+        const int side = (il == N - 1) ? 1 : 0;
+        const int kind = face_kind(a, a.nbr[e * 6 + 2 * l + side]);
+        if (kind == FACE_INVALID) continue;  // flagged by the main pass
+        double Al[3], An[3], qn[5], cb[5];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) Al[m] = An[m] = a.metric[(3 * l + m) * nodes + g];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            qn[c] = q[c];
+            cb[c] = -0.5 * isw * rb[c];
+        }
+        if (kind == FACE_INTERIOR) {
+            const long long nb = a.nbr[e * 6 + 2 * l + side];
+            const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
+            const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * st);
+            const long long pg = nb * N3 + k.lno;
+            const int lp = k.fp >> 1;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) An[m] = k.sg * a.metric[(3 * lp + m) * nodes + pg];
+            const double iJn = rcp(a.jac[pg]);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                qn[c] = a.q[c * nodes + pg];
+                cb[c] += 0.5 * isw * a.gbar[c * nodes + pg] * iJn;
+            }
+        } else if (kind == FACE_DIRICHLET) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
+        }
+        const double n0 = 0.5 * (Al[0] + An[0]), n1 = 0.5 * (Al[1] + An[1]), n2 = 0.5 * (Al[2] + An[2]);
+        const double ia2 = rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
+#pragma unroll 1
+        for (int k = 0; k < 5; ++k) {
+            Dual qd[5], qg[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                qd[c] = Dual(q[c], c == k ? 1.0 : 0.0);
+                qg[c] = Dual(qn[c]);
+            }
+            if (kind == FACE_WALL) {
+                // the own state with the momentum reversed
+                qg[0] = qd[0];
+                qg[4] = qd[4];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) qg[1 + m] = -qd[1 + m];
+            } else if (kind == FACE_SLIP) {
+                // the own state with the momentum reflected about the face
+                const Dual mn = (qd[1] * Al[0] + qd[2] * Al[1] + qd[3] * Al[2]) * ia2;
+                qg[0] = qd[0];
+                qg[4] = qd[4];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) qg[1 + m] = fma(-2.0 * mn, Al[m], qd[1 + m]);
+            }
+            const NodeT<Dual> mi = md_node(qd, gm1), mo = md_node(qg, gm1);
+            Dual md[5];
+            matrix_dissipation(mi, mo, n0, n1, n2, a.gamma, a.R, md);
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) t = fma(cb[c], md[c].d, t);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) qb[c] += c == k ? t : 0.0;  // no dynamic register index
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] += qb[c];
+}
+
 template <int N, int EPW, bool OR, int FLUX>
 int launch_vjp_f(const VjpArgs &a, hipStream_t s) {
     constexpr int NT = NT_OF(EPW * N * N * N);
@@ -983,7 +1102,12 @@ int launch_vjp_f(const VjpArgs &a, hipStream_t s) {
         if (hipGetLastError() != hipSuccess) return -1;
         hipLaunchKernelGGL((k_vjp_bnd<N, false, FLUX>), dim3((unsigned)nb), dim3(256), 0, s, a);
     }
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (a.iface_diss == 2) {
+        hipLaunchKernelGGL((k_vjp_md<N>), dim3((unsigned)((a.nodes + 255) / 256)), dim3(256), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return -1;
+    }
+    return 0;
 }
 
 template <int N, int EPW, bool OR>
