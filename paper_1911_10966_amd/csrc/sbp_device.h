@@ -25,9 +25,8 @@ __device__ __forceinline__ double rcp(double x) {
 // With z = (a-b)/(a+b) and u = z^2:  log(a/b) = 2 artanh z = 2 z F(u),  F(u) = sum_k u^k/(2k+1),
 // so the logarithmic mean is (a+b)/(2 F(u)) and its inverse 2 F(u)/(a+b).  For u < 1e-2 the
 // series below (F through u^7, G = 1/F through u^7) are accurate to < 1e-17 relative.
-template <class T>  // double, or ad::Dual in the matrix dissipation's derivative
-__device__ __forceinline__ T series_F(T u) {
-    T r = 1.0 / 15.0;
+__device__ __forceinline__ double series_F(double u) {
+    double r = 1.0 / 15.0;
     r = fma(r, u, 1.0 / 13.0);
     r = fma(r, u, 1.0 / 11.0);
     r = fma(r, u, 1.0 / 9.0);
@@ -36,10 +35,9 @@ __device__ __forceinline__ T series_F(T u) {
     r = fma(r, u, 1.0 / 3.0);
     return fma(r, u, 1.0);
 }
-template <class T>
-__device__ __forceinline__ T series_G(T u) {
+__device__ __forceinline__ double series_G(double u) {
     // coefficients of 1/F(u): g_k = -sum_{i=1..k} g_{k-i}/(2i+1), g_0 = 1
-    T r = -25865068.0 / 1915538625.0;
+    double r = -25865068.0 / 1915538625.0;
     r = fma(r, u, -10719068.0 / 638512875.0);
     r = fma(r, u, -10196.0 / 467775.0);
     r = fma(r, u, -428.0 / 14175.0);
@@ -51,42 +49,9 @@ __device__ __forceinline__ T series_G(T u) {
 
 constexpr double LOGMEAN_U = 1e-2;
 
-template <class T>
-struct NodeT {
-    T rho, u1, u2, u3, beta, lrho, lbeta, k;  // beta = rho / (2P) = 1/(2RT), k = |U|^2
+struct Node {
+    double rho, u1, u2, u3, beta, lrho, lbeta, k;  // beta = rho / (2P) = 1/(2RT), k = |U|^2
 };
-using Node = NodeT<double>;
-
-__device__ __forceinline__ double val(double x) { return x; }
-
-// Forward-mode dual numbers (a value and its derivative along one direction), for derivatives of
-// the matrix dissipation.  The functions live in their own namespace and are found by
-// argument-dependent lookup, so they never capture calls on plain doubles.
-namespace ad {
-struct Dual {
-    double v, d;
-    __device__ __forceinline__ Dual(double x = 0.0, double dx = 0.0) : v(x), d(dx) {}
-};
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, ::fma(a.v, b.d, a.d * b.v)); }
-__device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
-__device__ __forceinline__ Dual fma(Dual a, Dual b, Dual c) {
-    return Dual(::fma(a.v, b.v, c.v), ::fma(a.v, b.d, ::fma(a.d, b.v, c.d)));
-}
-__device__ __forceinline__ Dual rcp(Dual x) {
-    const double r = sbp::rcp(x.v);
-    return Dual(r, -x.d * r * r);
-}
-__device__ __forceinline__ Dual sqrt(Dual x) {
-    const double s = ::sqrt(x.v);
-    return Dual(s, 0.5 * x.d * sbp::rcp(s));
-}
-__device__ __forceinline__ Dual fabs(Dual x) { return x.v >= 0.0 ? x : -x; }
-__device__ __forceinline__ Dual log(Dual x) { return Dual(::log(x.v), x.d * sbp::rcp(x.v)); }
-__device__ __forceinline__ double val(Dual x) { return x.v; }
-}  // namespace ad
 
 __device__ __forceinline__ void primitives(const double q[5], double gm1, Node &n, double &P,
                                            bool &ok) {
@@ -287,32 +252,30 @@ __device__ __forceinline__ ResArgs problem_view(const GroupArgs &g, const ProbDe
 // (own) and b (partner), n = (n0, n1, n2) the averaged metric row: the Roe-type dissipation in
 // entropy variables, eigenvectors of the flux Jacobian in n/|n| at the Chandrashekar-flux averages,
 // scaled so that R T R^T = dq/dw.  Both nodes carry their logarithms.
-template <class T>  // double, or ad::Dual for its directional derivatives
-__device__ __forceinline__ void matrix_dissipation(const NodeT<T> &a, const NodeT<T> &b, double n0,
-                                                   double n1, double n2, double gamma, double R,
-                                                   T out[5]) {
+__device__ __forceinline__ void matrix_dissipation(const Node &a, const Node &b, double n0, double n1,
+                                                   double n2, double gamma, double R, double out[5]) {
     const double gm1 = gamma - 1.0;
     // logarithmic means of rho and beta (series near equal states, as in the flux)
-    const T sr = a.rho + b.rho, dr = a.rho - b.rho;
-    const T sb = a.beta + b.beta, db = a.beta - b.beta;
-    const T irb = rcp(sr * sb);
-    const T isr = sb * irb, isb = sr * irb;
-    const T zr = dr * isr, ur = zr * zr;
-    const T rho_hat = val(ur) < LOGMEAN_U ? 0.5 * sr * series_G(ur) : dr * rcp(a.lrho - b.lrho);
-    const T zb = db * isb, ub_ = zb * zb;
-    const T ibeta_hat = val(ub_) < LOGMEAN_U ? 2.0 * isb * series_F(ub_) : (a.lbeta - b.lbeta) * rcp(db);
-    const T p_hat = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
-    const T a_hat = sqrt(gamma * p_hat * rcp(rho_hat));
-    const T u1 = 0.5 * (a.u1 + b.u1), u2 = 0.5 * (a.u2 + b.u2), u3 = 0.5 * (a.u3 + b.u3);
-    const T ubsq = u1 * u1 + u2 * u2 + u3 * u3;
-    const T h_hat = 0.5 * gamma / gm1 * ibeta_hat + ubsq - 0.25 * (a.k + b.k);
+    const double sr = a.rho + b.rho, dr = a.rho - b.rho;
+    const double sb = a.beta + b.beta, db = a.beta - b.beta;
+    const double irb = rcp(sr * sb);
+    const double isr = sb * irb, isb = sr * irb;
+    const double zr = dr * isr, ur = zr * zr;
+    const double rho_hat = ur < LOGMEAN_U ? 0.5 * sr * series_G(ur) : dr * rcp(a.lrho - b.lrho);
+    const double zb = db * isb, ub_ = zb * zb;
+    const double ibeta_hat = ub_ < LOGMEAN_U ? 2.0 * isb * series_F(ub_) : (a.lbeta - b.lbeta) * rcp(db);
+    const double p_hat = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
+    const double a_hat = sqrt(gamma * p_hat * rcp(rho_hat));
+    const double u1 = 0.5 * (a.u1 + b.u1), u2 = 0.5 * (a.u2 + b.u2), u3 = 0.5 * (a.u3 + b.u3);
+    const double ubsq = u1 * u1 + u2 * u2 + u3 * u3;
+    const double h_hat = 0.5 * gamma / gm1 * ibeta_hat + ubsq - 0.25 * (a.k + b.k);
     const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
     const double inn = rcp(nn);
     const double e0 = n0 * inn, e1 = n1 * inn, e2 = n2 * inn;
-    const T vn = u1 * e0 + u2 * e1 + u3 * e2;
+    const double vn = u1 * e0 + u2 * e1 + u3 * e2;
     // entropy-variable jump (w_1 up to a constant that cancels)
     const double R2 = 2.0 * R;
-    T dw[5];
+    double dw[5];
     dw[0] = R * ((a.lbeta - b.lbeta) / gm1 + (a.lrho - b.lrho) - (a.beta * a.k - b.beta * b.k));
     dw[1] = R2 * (a.beta * a.u1 - b.beta * b.u1);
     dw[2] = R2 * (a.beta * a.u2 - b.beta * b.u2);
@@ -320,40 +283,40 @@ __device__ __forceinline__ void matrix_dissipation(const NodeT<T> &a, const Node
     dw[4] = -R2 * (a.beta - b.beta);
     const double iR = rcp(R);
     // acoustic waves
-    const T ca = rho_hat * iR / (2.0 * gamma);
+    const double ca = rho_hat * iR / (2.0 * gamma);
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[c] = 0.0;
 #pragma unroll
     for (int sg = -1; sg <= 1; sg += 2) {
         const double s = (double)sg;
-        const T r[5] = {1.0, fma(s * a_hat, e0, u1), fma(s * a_hat, e1, u2), fma(s * a_hat, e2, u3),
-                        fma(s * a_hat, vn, h_hat)};
-        const T proj = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
-        const T k = fabs(fma(s, a_hat, vn)) * ca * proj;
+        const double r[5] = {1.0, fma(s * a_hat, e0, u1), fma(s * a_hat, e1, u2), fma(s * a_hat, e2, u3),
+                             fma(s * a_hat, vn, h_hat)};
+        const double proj = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
+        const double k = fabs(fma(s, a_hat, vn)) * ca * proj;
 #pragma unroll
         for (int c = 0; c < 5; ++c) out[c] = fma(k, r[c], out[c]);
     }
     // entropy wave
     {
-        const T r[5] = {1.0, u1, u2, u3, 0.5 * ubsq};
-        const T proj = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
-        const T k = fabs(vn) * rho_hat * gm1 / gamma * iR * proj;
+        const double r[5] = {1.0, u1, u2, u3, 0.5 * ubsq};
+        const double proj = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
+        const double k = fabs(vn) * rho_hat * gm1 / gamma * iR * proj;
 #pragma unroll
         for (int c = 0; c < 5; ++c) out[c] = fma(k, r[c], out[c]);
     }
     // shear waves: (I - e e^T) acting on v = dw_U + U_bar dw_5
     {
-        const T v0 = fma(u1, dw[4], dw[1]), v1 = fma(u2, dw[4], dw[2]), v2 = fma(u3, dw[4], dw[3]);
-        const T ve = v0 * e0 + v1 * e1 + v2 * e2;
-        const T t0 = v0 - ve * e0, t1 = v1 - ve * e1, t2 = v2 - ve * e2;
-        const T k = fabs(vn) * p_hat * iR;
+        const double v0 = fma(u1, dw[4], dw[1]), v1 = fma(u2, dw[4], dw[2]), v2 = fma(u3, dw[4], dw[3]);
+        const double ve = v0 * e0 + v1 * e1 + v2 * e2;
+        const double t0 = v0 - ve * e0, t1 = v1 - ve * e1, t2 = v2 - ve * e2;
+        const double k = fabs(vn) * p_hat * iR;
         out[1] = fma(k, t0, out[1]);
         out[2] = fma(k, t1, out[2]);
         out[3] = fma(k, t2, out[3]);
         out[4] = fma(k, u1 * t0 + u2 * t1 + u3 * t2, out[4]);
     }
 #pragma unroll
-    for (int c = 0; c < 5; ++c) out[c] = out[c] * nn;
+    for (int c = 0; c < 5; ++c) out[c] *= nn;
 }
 
 // Data of the partner node of a face node: state, metric row of the face direction and, when the

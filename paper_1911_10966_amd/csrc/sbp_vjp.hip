@@ -11,7 +11,7 @@
 //                gradient operator with its SAT (reading neighbour theta cotangents), and the map
 //                from primitive cotangents to qbar.
 // Two passes add to qbar afterwards: k_vjp_bnd the boundary faces, and k_vjp_md the matrix
-// interface dissipation (iface_diss = 2), whose derivative is taken in forward mode.
+// interface dissipation (iface_diss = 2).
 // Pair terms of the flux-differencing sum use the same cyclic pairing and LDS mailbox as the
 // forward kernel; cotangents are accumulated on the node quantities (rho, U, beta) and mapped to
 // conservative variables once per node.
@@ -968,33 +968,203 @@ __global__ void __launch_bounds__(256) k_vjp_bnd(const VjpArgs a) {
         bnd_node<N, VISC, FLUX>(a, g);
 }
 
+// Reverse of matrix_dissipation (sbp_device.h): cotangents of both nodes' quantities from the
+// cotangent ob of its output.  The forward values are recomputed first; the reverse then walks
+// the shear, entropy and acoustic waves, the entropy-variable jump and the averages.
+__device__ __forceinline__ void matrix_dissipation_vjp(const Node &a, const Node &b, double n0,
+                                                       double n1, double n2, double gamma, double R,
+                                                       const double ob[5], NodeBar &ab, NodeBar &bb) {
+    const double gm1 = gamma - 1.0;
+    // ---- forward values
+    const double sr = a.rho + b.rho, dr = a.rho - b.rho;
+    const double sb = a.beta + b.beta, db = a.beta - b.beta;
+    const double irb = rcp(sr * sb);
+    const double isr = sb * irb, isb = sr * irb;
+    const double zr = dr * isr, ur = zr * zr;
+    const bool ser_r = ur < LOGMEAN_U;
+    const double Gr = ser_r ? series_G(ur) : 0.0;
+    const double iLr = ser_r ? 0.0 : rcp(a.lrho - b.lrho);
+    const double rho_hat = ser_r ? 0.5 * sr * Gr : dr * iLr;
+    const double zb = db * isb, ub_ = zb * zb;
+    const bool ser_b = ub_ < LOGMEAN_U;
+    const double Fb = ser_b ? series_F(ub_) : 0.0;
+    const double idb = ser_b ? 0.0 : rcp(db);
+    const double ibeta_hat = ser_b ? 2.0 * isb * Fb : (a.lbeta - b.lbeta) * idb;
+    const double p_hat = 0.5 * sr * isb;
+    const double irh = rcp(rho_hat);
+    const double a_hat = sqrt(gamma * p_hat * irh);
+    const double u[3] = {0.5 * (a.u1 + b.u1), 0.5 * (a.u2 + b.u2), 0.5 * (a.u3 + b.u3)};
+    const double ubsq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double h_hat = 0.5 * gamma / gm1 * ibeta_hat + ubsq - 0.25 * (a.k + b.k);
+    const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    const double inn = rcp(nn);
+    const double en[3] = {n0 * inn, n1 * inn, n2 * inn};
+    const double vn = u[0] * en[0] + u[1] * en[1] + u[2] * en[2];
+    const double R2 = 2.0 * R;
+    const double ua[3] = {a.u1, a.u2, a.u3}, uo[3] = {b.u1, b.u2, b.u3};
+    double dw[5];
+    dw[0] = R * ((a.lbeta - b.lbeta) / gm1 + (a.lrho - b.lrho) - (a.beta * a.k - b.beta * b.k));
+#pragma unroll
+    for (int m = 0; m < 3; ++m) dw[1 + m] = R2 * (a.beta * ua[m] - b.beta * uo[m]);
+    dw[4] = -R2 * (a.beta - b.beta);
+    const double iR = rcp(R);
+    const double ca = rho_hat * iR / (2.0 * gamma);
+    const double svn = vn >= 0.0 ? 1.0 : -1.0, avn = fabs(vn);
+
+    // ---- reverse
+    double S[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) S[c] = nn * ob[c];
+    double rhb = 0.0, ibhb = 0.0, phb = 0.0, ahb = 0.0, hb = 0.0, vnb = 0.0, usqb = 0.0, cab = 0.0;
+    double uba[3] = {0.0, 0.0, 0.0};  // cotangent of the averaged velocity
+    double dwb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // shear waves: out_U += ks t, out_E += ks (u.t), t = (I - e e^T) v, v = dw_U + u dw_4
+    {
+        double v[3], t[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m] = fma(u[m], dw[4], dw[1 + m]);
+        const double ve = v[0] * en[0] + v[1] * en[1] + v[2] * en[2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) t[m] = v[m] - ve * en[m];
+        const double ks = avn * p_hat * iR;
+        const double ut = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+        const double ksb = S[1] * t[0] + S[2] * t[1] + S[3] * t[2] + S[4] * ut;
+        double tb[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            tb[m] = ks * fma(S[4], u[m], S[1 + m]);
+            uba[m] += ks * S[4] * t[m];
+        }
+        const double te = tb[0] * en[0] + tb[1] * en[1] + tb[2] * en[2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double vb = tb[m] - te * en[m];
+            uba[m] += vb * dw[4];
+            dwb[4] += vb * u[m];
+            dwb[1 + m] += vb;
+        }
+        vnb += svn * p_hat * iR * ksb;
+        phb += avn * iR * ksb;
+    }
+    // entropy wave: out += ke re, re = [1, u, |u|^2/2], ke = |vn| rho_hat (gm1/gamma)/R (re.dw)
+    {
+        const double ce = gm1 / gamma * iR;
+        const double re[5] = {1.0, u[0], u[1], u[2], 0.5 * ubsq};
+        const double pe = re[0] * dw[0] + re[1] * dw[1] + re[2] * dw[2] + re[3] * dw[3] + re[4] * dw[4];
+        const double ke = avn * rho_hat * ce * pe;
+        const double keb = S[0] * re[0] + S[1] * re[1] + S[2] * re[2] + S[3] * re[3] + S[4] * re[4];
+        const double peb = avn * rho_hat * ce * keb;
+        vnb += svn * rho_hat * ce * pe * keb;
+        rhb += avn * ce * pe * keb;
+        // re's cotangent: ke S + peb dw
+#pragma unroll
+        for (int m = 0; m < 3; ++m) uba[m] += fma(ke, S[1 + m], peb * dw[1 + m]);
+        usqb += 0.5 * fma(ke, S[4], peb * dw[4]);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) dwb[c] += peb * re[c];
+    }
+    // acoustic waves: out += k r, r = [1, u + s a e, h + s a vn], k = |vn + s a| ca (r.dw)
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+        const double sv = (double)sg;
+        const double r[5] = {1.0, fma(sv * a_hat, en[0], u[0]), fma(sv * a_hat, en[1], u[1]),
+                             fma(sv * a_hat, en[2], u[2]), fma(sv * a_hat, vn, h_hat)};
+        const double pr = r[0] * dw[0] + r[1] * dw[1] + r[2] * dw[2] + r[3] * dw[3] + r[4] * dw[4];
+        const double lam = fma(sv, a_hat, vn);
+        const double alam = fabs(lam), slam = lam >= 0.0 ? 1.0 : -1.0;
+        const double k = alam * ca * pr;
+        const double kb = S[0] * r[0] + S[1] * r[1] + S[2] * r[2] + S[3] * r[3] + S[4] * r[4];
+        const double lamb = slam * ca * pr * kb;
+        cab += alam * pr * kb;
+        const double prb = alam * ca * kb;
+        double rbv[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            rbv[c] = fma(k, S[c], prb * dw[c]);
+            dwb[c] += prb * r[c];
+        }
+        vnb += lamb;
+        ahb += sv * lamb;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) uba[m] += rbv[1 + m];
+        ahb += sv * (rbv[1] * en[0] + rbv[2] * en[1] + rbv[3] * en[2] + rbv[4] * vn);
+        hb += rbv[4];
+        vnb += sv * a_hat * rbv[4];
+    }
+    rhb += cab * iR / (2.0 * gamma);
+    // entropy-variable jump
+    ab.lbeta = R * dwb[0] / gm1;
+    bb.lbeta = -ab.lbeta;
+    ab.lrho = R * dwb[0];
+    bb.lrho = -ab.lrho;
+    ab.beta = -R * dwb[0] * a.k - R2 * dwb[4];
+    bb.beta = R * dwb[0] * b.k + R2 * dwb[4];
+    ab.k = -R * dwb[0] * a.beta;
+    bb.k = R * dwb[0] * b.beta;
+    double uab[3], uob[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        ab.beta += R2 * dwb[1 + m] * ua[m];
+        bb.beta -= R2 * dwb[1 + m] * uo[m];
+        uab[m] = R2 * dwb[1 + m] * a.beta;
+        uob[m] = -R2 * dwb[1 + m] * b.beta;
+    }
+    // averages: vn = u.e, h_hat, |u|^2, u = (u_a + u_b)/2
+#pragma unroll
+    for (int m = 0; m < 3; ++m) uba[m] += vnb * en[m];
+    ibhb += 0.5 * gamma / gm1 * hb;
+    usqb += hb;
+    ab.k -= 0.25 * hb;
+    bb.k -= 0.25 * hb;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        uba[m] += 2.0 * u[m] * usqb;
+        uab[m] += 0.5 * uba[m];
+        uob[m] += 0.5 * uba[m];
+    }
+    ab.u1 = uab[0]; ab.u2 = uab[1]; ab.u3 = uab[2];
+    bb.u1 = uob[0]; bb.u2 = uob[1]; bb.u3 = uob[2];
+    // a_hat = sqrt(gamma p_hat / rho_hat), p_hat = sr / (2 sb)
+    phb += ahb * a_hat / (2.0 * p_hat);
+    rhb -= ahb * a_hat * irh * 0.5;
+    double srb = 0.5 * phb * isb, sbb = -p_hat * phb * isb, drb = 0.0, dbb = 0.0;
+    // logarithmic means
+    if (ser_r) {
+        srb += 0.5 * Gr * rhb;
+        const double urb = rhb * 0.5 * sr * series_Gp(ur);
+        drb += urb * 2.0 * zr * isr;
+        srb -= urb * 2.0 * ur * isr;
+    } else {
+        drb += rhb * iLr;
+        const double Lb = -rhb * rho_hat * iLr;
+        ab.lrho += Lb;
+        bb.lrho -= Lb;
+    }
+    if (ser_b) {
+        sbb -= ibeta_hat * isb * ibhb;
+        const double ubb = ibhb * 2.0 * isb * series_Fp(ub_);
+        dbb += ubb * 2.0 * zb * isb;
+        sbb -= ubb * 2.0 * ub_ * isb;
+    } else {
+        ab.lbeta += ibhb * idb;
+        bb.lbeta -= ibhb * idb;
+        dbb -= ibhb * ibeta_hat * idb;
+    }
+    ab.rho = srb + drb;
+    bb.rho = srb - drb;
+    ab.beta += sbb + dbb;
+    bb.beta += sbb - dbb;
+}
+
 // ------------------------------------------------------------------------------------------
 // Pass 4 (iface_diss = 2): the matrix interface dissipation, one thread per node; adds to qbar.
 // Across an interior face the two sides' terms are -M(q_i, q_nu)/(2 w_end) and its negative (M is
 // odd in the exchange of the states and even in the sign of the normal), so the own node's
 // cotangent is (dM/dq_i)^T applied to -(rbar_i - rbar_nu)/(2 w_end).  A boundary ghost has no
 // cotangent of its own; a wall ghost is an image of the own state and is differentiated with it.
-// dM/dq_i is taken in forward mode, one own-state component at a time (five evaluations of M).
 // ------------------------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ NodeT<T> md_node(const T q[5], double gm1) {
-    NodeT<T> n;
-    n.rho = q[0];
-    const T ir = rcp(q[0]);
-    n.u1 = q[1] * ir;
-    n.u2 = q[2] * ir;
-    n.u3 = q[3] * ir;
-    n.k = n.u1 * n.u1 + n.u2 * n.u2 + n.u3 * n.u3;
-    const T P = gm1 * (q[4] - 0.5 * q[0] * n.k);
-    n.beta = 0.5 * q[0] * rcp(P);
-    n.lrho = log(q[0]);
-    n.lbeta = log(n.beta);
-    return n;
-}
-
 template <int N>
 __global__ void __launch_bounds__(256) k_vjp_md(const VjpArgs a) {
-    using ad::Dual;
     constexpr int N2 = N * N, N3 = N * N * N;
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.nodes) return;
@@ -1005,13 +1175,18 @@ __global__ void __launch_bounds__(256) k_vjp_md(const VjpArgs a) {
     const long long nodes = a.nodes;
     const double gm1 = a.gamma - 1.0;
     const double isw = 1.0 / a.w_end;
-    double q[5], rb[5], qb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double q[5], rb[5];
     const double iJ = rcp(a.jac[g]);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         q[c] = a.q[c * nodes + g];
         rb[c] = a.gbar[c * nodes + g] * iJ;
     }
+    Node me;
+    double Pme;
+    bool ok;
+    primitives(q, gm1, me, Pme, ok);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // cotangents of rho, U, beta
 #pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         // (selects rather than indexed arrays: the loop is not unrolled)
@@ -1019,18 +1194,15 @@ __global__ void __launch_bounds__(256) k_vjp_md(const VjpArgs a) {
         const int st = l == 0 ? 1 : (l == 1 ? N : N2);
         if (il != 0 && il != N - 1) continue;
         const int side = (il == N - 1) ? 1 : 0;
-        const int kind = face_kind(a, a.nbr[e * 6 + 2 * l + side]);
+        const long long nb = a.nbr[e * 6 + 2 * l + side];
+        const int kind = face_kind(a, nb);
         if (kind == FACE_INVALID) continue;  // flagged by the main pass
         double Al[3], An[3], qn[5], cb[5];
 #pragma unroll
         for (int m = 0; m < 3; ++m) Al[m] = An[m] = a.metric[(3 * l + m) * nodes + g];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            qn[c] = q[c];
-            cb[c] = -0.5 * isw * rb[c];
-        }
+        for (int c = 0; c < 5; ++c) cb[c] = -0.5 * isw * rb[c];
         if (kind == FACE_INTERIOR) {
-            const long long nb = a.nbr[e * 6 + 2 * l + side];
             const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
             const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * st);
             const long long pg = nb * N3 + k.lno;
@@ -1046,41 +1218,51 @@ __global__ void __launch_bounds__(256) k_vjp_md(const VjpArgs a) {
         } else if (kind == FACE_DIRICHLET) {
 #pragma unroll
             for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
-        }
-        const double n0 = 0.5 * (Al[0] + An[0]), n1 = 0.5 * (Al[1] + An[1]), n2 = 0.5 * (Al[2] + An[2]);
-        const double ia2 = rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
-#pragma unroll 1
-        for (int k = 0; k < 5; ++k) {
-            Dual qd[5], qg[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                qd[c] = Dual(q[c], c == k ? 1.0 : 0.0);
-                qg[c] = Dual(qn[c]);
-            }
+        } else {
+            // wall ghosts: the own state with the momentum reversed (no-slip) or reflected about
+            // the face (slip)
+            qn[0] = q[0];
+            qn[4] = q[4];
             if (kind == FACE_WALL) {
-                // the own state with the momentum reversed
-                qg[0] = qd[0];
-                qg[4] = qd[4];
+                qn[1] = -q[1]; qn[2] = -q[2]; qn[3] = -q[3];
+            } else {
+                const double mn = (q[1] * Al[0] + q[2] * Al[1] + q[3] * Al[2]) *
+                                  rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
 #pragma unroll
-                for (int m = 0; m < 3; ++m) qg[1 + m] = -qd[1 + m];
-            } else if (kind == FACE_SLIP) {
-                // the own state with the momentum reflected about the face
-                const Dual mn = (qd[1] * Al[0] + qd[2] * Al[1] + qd[3] * Al[2]) * ia2;
-                qg[0] = qd[0];
-                qg[4] = qd[4];
-#pragma unroll
-                for (int m = 0; m < 3; ++m) qg[1 + m] = fma(-2.0 * mn, Al[m], qd[1 + m]);
+                for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, Al[m], q[1 + m]);
             }
-            const NodeT<Dual> mi = md_node(qd, gm1), mo = md_node(qg, gm1);
-            Dual md[5];
-            matrix_dissipation(mi, mo, n0, n1, n2, a.gamma, a.R, md);
-            double t = 0.0;
+        }
+        Node o;
+        double Pn;
+        primitives_nolog(qn, gm1, o, Pn);
+        o.lrho = log(o.rho);
+        o.lbeta = log(o.beta);
+        NodeBar ab, bb;
+        matrix_dissipation_vjp(me, o, 0.5 * (Al[0] + An[0]), 0.5 * (Al[1] + An[1]), 0.5 * (Al[2] + An[2]),
+                               a.gamma, a.R, cb, ab, bb);
+        double ra[5];
+        reduce_bar(me, ab, ra);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) t = fma(cb[c], md[c].d, t);
+        for (int c = 0; c < 5; ++c) acc[c] += ra[c];
+        if (kind == FACE_WALL || kind == FACE_SLIP) {
+            // the ghost's rho and beta are the own ones; its velocity the reversed or reflected one
+            double rg[5];
+            reduce_bar(o, bb, rg);
+            acc[0] += rg[0];
+            acc[4] += rg[4];
+            if (kind == FACE_WALL) {
+                acc[1] -= rg[1]; acc[2] -= rg[2]; acc[3] -= rg[3];
+            } else {
+                const double un = (rg[1] * Al[0] + rg[2] * Al[1] + rg[3] * Al[2]) *
+                                  rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) qb[c] += c == k ? t : 0.0;  // no dynamic register index
+                for (int m = 0; m < 3; ++m) acc[1 + m] += rg[1 + m] - 2.0 * un * Al[m];
+            }
         }
     }
+    double ub[3] = {acc[1], acc[2], acc[3]};
+    double qb[5];
+    prim_vjp(q, gm1, a.R, acc[0], ub, acc[4], 0.0, 0.0, qb);
 #pragma unroll
     for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] += qb[c];
 }
