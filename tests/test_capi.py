@@ -78,3 +78,37 @@ def test_argument_errors_on_host():
     bcm = (_lib.sbp_problem * 1)(_lib.sbp_problem(3, 1, 8, 64, 64, 64, 1.4, 1.0, 0.0, 0.72, 1.0, 0, 0, 68, 0))
     assert L.sbp_residual(bcm, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
     assert P.lib().sbp_error_string(_lib.SBP_ERR_WORKSPACE).decode().startswith("workspace")
+
+
+def _prob(**kw):
+    f = dict(p=3, iface_diss=1, n_elem=8, nbr=64, metric=64, jac=64, gamma=1.4, R=1.0, mu=0.0, Pr=0.72,
+             eta=1.0, two_point=0, reserved=0, bc_state=None, source=None, face_orient=None)
+    f.update(kw)
+    return (_lib.sbp_problem * 1)(_lib.sbp_problem(**f))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_elem=0), dict(n_elem=-3),                         # empty or negative element count
+    dict(gamma=1.0), dict(R=0.0), dict(mu=-1e-3), dict(eta=-1.0),  # gas and penalty constants
+    dict(mu=1e-3, Pr=0.0),                                    # viscous problem without Prandtl number
+    dict(reserved=1), dict(two_point=4), dict(iface_diss=-1),
+    dict(iface_diss=2, two_point=1),                          # matrix dissipation needs ES-C or SF-KG
+    dict(nbr=None), dict(nbr=66), dict(jac=None),             # missing or misaligned arrays
+    dict(face_orient=66), dict(source=68),
+])
+def test_invalid_problems_are_rejected_before_any_device_work(kw):
+    L = P.lib()
+    arr = _prob(**kw)
+    assert L.sbp_workspace_bytes(arr, 1) == 0
+    for rc in (L.sbp_residual(arr, 1, 64, 128, 256, 1 << 20, None),
+               L.sbp_rk_step(arr, 1, 64, 128, 1, 256, 1 << 20, None),
+               L.sbp_residual_vjp(arr, 1, 64, 128, 192, 256, 1 << 22, None)):
+        assert rc in (_lib.SBP_ERR_ARG, _lib.SBP_ERR_DEGREE), (kw, rc)
+
+
+def test_empty_problem_list_is_rejected():
+    L = P.lib()
+    arr = _prob()
+    assert L.sbp_residual(arr, 0, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
+    assert L.sbp_residual(None, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
+    assert L.sbp_workspace_bytes(arr, 0) == 0
