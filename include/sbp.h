@@ -157,10 +157,9 @@ int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const doubl
 /* Vector-Jacobian product qbar = (d(dq/dt)/dq)^T gbar of the residual of sbp_residual, with each
  * element recomputing its forward intermediates (no two-point fluxes are stored) and interface
  * terms gathered from both sides (no atomics).  q, gbar, qbar: device, same layout as q; qbar must
- * not alias q or gbar.  Available for the Chandrashekar (ES-C) and Kennedy-Gruber (SF-KG) volume
- * forms (two_point 0 or 2) with any interface dissipation (iface_diss 0, 1 or 2), on periodic or
- * bounded problems (Dirichlet data is held fixed; wall ghosts are differentiated through the own
- * state) and with or without a face_orient table; the central and DC forms give SBP_ERR_ARG,
+ * not alias q or gbar.  Available for every volume form (two_point 0..3) and interface dissipation
+ * that sbp_residual accepts, on periodic or bounded problems (Dirichlet data is held fixed; wall
+ * ghosts are differentiated through the own state) and with or without a face_orient table;
  * degrees above SBP_MAX_VJP_P give SBP_ERR_DEGREE, and invalid neighbour or orientation entries
  * raise the mesh flag as in sbp_residual.  A source term does not enter the product.  Non-smooth
  * points follow fixed conventions: d|x|/dx = +1 at x = 0, and the maximum in the Lax-Friedrichs

@@ -547,12 +547,8 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     if (rc != SBP_OK) return rc;
     if (!aligned8(q) || !aligned8(gbar) || !aligned8(qbar) || qbar == q || qbar == gbar)
         return SBP_ERR_ARG;
-    for (int b = 0; b < n_prob; ++b) {
-        if (probs[b].two_point != SBP_FLUX_CHANDRASHEKAR &&
-            probs[b].two_point != SBP_FLUX_KENNEDY_GRUBER)
-            return SBP_ERR_ARG;
+    for (int b = 0; b < n_prob; ++b)
         if (probs[b].p > SBP_MAX_VJP_P) return SBP_ERR_DEGREE;
-    }
     char *w = static_cast<char *>(ws);
     size_t off = 0;
     for (int b = 0; b < n_prob; ++b) {

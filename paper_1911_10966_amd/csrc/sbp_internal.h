@@ -140,7 +140,7 @@ struct VjpArgs {
     double gamma, R, mu, Pr, eta;
     double w_end;
     int iface_diss;
-    int two_point;         // volume form: 0 Chandrashekar, 2 Kennedy-Gruber
+    int two_point;         // volume form: 0 Chandrashekar, 1 central, 2 Kennedy-Gruber, 3 standard DC
 };
 int launch_vjp(int p, const VjpArgs &a, hipStream_t s);
 int launch_metrics(int p, long long K, const double *x, double *metric, double *jac,

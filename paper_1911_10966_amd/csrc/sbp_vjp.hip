@@ -170,12 +170,52 @@ __device__ __forceinline__ void kg_flux_n_vjp(const Node &a, const Node &b, doub
     ab.k = bb.k = 0.25 * Ebarb;
 }
 
-// Reverse of the two-point flux of the volume form FLUX (0 Chandrashekar, 2 Kennedy-Gruber).
+// Reverse of the nodal inviscid flux contracted with n, F(a).n = [rho U_n, rho U_n U + P n,
+// rho U_n H] with P = rho/(2 beta) and H = gamma/(2 (gamma-1) beta) + |U|^2/2; adds the
+// cotangents of a's quantities for the output cotangent fb to ab.
+__device__ __forceinline__ void euler_flux_n_vjp(const Node &a, double n0, double n1, double n2,
+                                                 double gm1, const double fb[5], NodeBar &ab) {
+    const double un = a.u1 * n0 + a.u2 * n1 + a.u3 * n2;
+    const double m = a.rho * un;
+    const double ib = 1.0 / a.beta;
+    const double g2 = 0.5 * (gm1 + 1.0) / gm1;
+    const double H = fma(g2, ib, 0.5 * a.k);
+    const double mb = fb[0] + fb[1] * a.u1 + fb[2] * a.u2 + fb[3] * a.u3 + fb[4] * H;
+    const double Pb = fb[1] * n0 + fb[2] * n1 + fb[3] * n2;
+    const double Hb = fb[4] * m;
+    ab.u1 += fb[1] * m + mb * a.rho * n0;
+    ab.u2 += fb[2] * m + mb * a.rho * n1;
+    ab.u3 += fb[3] * m + mb * a.rho * n2;
+    ab.rho += mb * un + 0.5 * Pb * ib;
+    ab.beta -= (0.5 * Pb * a.rho + Hb * g2) * ib * ib;
+    ab.k += 0.5 * Hb;
+}
+
+__device__ __forceinline__ void zero_bar(NodeBar &z) {
+    z.rho = z.u1 = z.u2 = z.u3 = z.beta = z.lrho = z.lbeta = z.k = 0.0;
+}
+
+// Reverse of flux_n<1> (central flux (F(a) + F(b))/2 contracted with n).
+__device__ __forceinline__ void central_flux_n_vjp(const Node &a, const Node &b, double n0, double n1,
+                                                   double n2, double gm1, const double fb[5],
+                                                   NodeBar &ab, NodeBar &bb) {
+    double h[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) h[c] = 0.5 * fb[c];
+    zero_bar(ab);
+    zero_bar(bb);
+    euler_flux_n_vjp(a, n0, n1, n2, gm1, h, ab);
+    euler_flux_n_vjp(b, n0, n1, n2, gm1, h, bb);
+}
+
+// Reverse of the two-point flux of the volume form FLUX (0 Chandrashekar, 1 central,
+// 2 Kennedy-Gruber; the standard DC form 3 uses the central flux at interfaces).
 template <int FLUX, bool LAZY = false>
 __device__ __forceinline__ void two_point_vjp(const Node &a, const Node &b, double n0, double n1,
                                               double n2, double gm1, const double fb[5], NodeBar &ab,
                                               NodeBar &bb) {
     if constexpr (FLUX == 2) kg_flux_n_vjp(a, b, n0, n1, n2, gm1, fb, ab, bb);
+    else if constexpr (FLUX == 1 || FLUX == 3) central_flux_n_vjp(a, b, n0, n1, n2, gm1, fb, ab, bb);
     else flux_n_vjp<LAZY>(a, b, n0, n1, n2, gm1, fb, ab, bb);
 }
 
@@ -501,6 +541,13 @@ __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, 
     for (int c = 0; c < 5; ++c) fb[c] = -s * isw * (rb[c] - rbn[c]);
     NodeBar ab, bb;
     two_point_vjp<FLUX, true>(me, o, n0, n1, n2, gm1, fb, ab, bb);
+    if constexpr (FLUX == 3) {
+        // the DC form keeps the own-flux part of the SAT: +(s/w_end) F(q_i).A_i
+        double fo[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fo[c] = s * isw * rb[c];
+        euler_flux_n_vjp(me, Al[0], Al[1], Al[2], gm1, fo, ab);
+    }
     double ra[5];
     reduce_bar(me, ab, ra);
 #pragma unroll
@@ -673,68 +720,96 @@ k_vjp_main(const VjpArgs a) {
     double qdir[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     // ---- inviscid volume pairs ------------------------------------------------------------
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        if (tid < NODES) {
-            s_buf[(F_A + 0) * NODES + tid] = A[l][0];
-            s_buf[(F_A + 1) * NODES + tid] = A[l][1];
-            s_buf[(F_A + 2) * NODES + tid] = A[l][2];
-        }
+    if constexpr (FLUX == 3) {
+        // standard DC form, -sum_l D_l (A_l . F(q)): the transposed line operator applied to
+        // rbar, then the reverse of the node's own contracted flux
         __syncthreads();
-        const int il = idx[l];
-        const int st = stride[l];
-        auto pair = [&](int b, bool send) {
-            const int pn = tid + (b - il) * st;
-            Node o;
-            o.rho = s_buf[F_RHO * NODES + pn];
-            o.u1 = s_buf[F_U1 * NODES + pn];
-            o.u2 = s_buf[F_U2 * NODES + pn];
-            o.u3 = s_buf[F_U3 * NODES + pn];
-            o.beta = s_buf[F_B * NODES + pn];
-            o.lrho = s_buf[F_LR * NODES + pn];
-            o.lbeta = s_buf[F_LB * NODES + pn];
-            o.k = s_buf[F_K * NODES + pn];
-            const double n0 = A[l][0] + s_buf[(F_A + 0) * NODES + pn];
-            const double n1 = A[l][1] + s_buf[(F_A + 1) * NODES + pn];
-            const double n2 = A[l][2] + s_buf[(F_A + 2) * NODES + pn];
-            const double dab = s_D[il * N + b], dba = s_D[b * N + il];
-            double fb[5];
+        if (tid < NODES) {
+            NodeBar vb;
+            zero_bar(vb);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) fb[c] = -dab * rb[c] - dba * s_buf[(F_RB + c) * NODES + pn];
-            NodeBar ab, bb;
-            two_point_vjp<FLUX>(me, o, n0, n1, n2, gm1, fb, ab, bb);
+            for (int l = 0; l < 3; ++l) {
+                const int il = idx[l];
+                double cl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    const double dd = s_D[b * N + il];
+                    const int pn = tid + (b - il) * stride[l];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) cl[c] = fma(-dd, s_buf[(F_RB + c) * NODES + pn], cl[c]);
+                }
+                euler_flux_n_vjp(me, A[l][0], A[l][1], A[l][2], gm1, cl, vb);
+            }
             double ra[5];
-            reduce_bar(me, ab, ra);
+            reduce_bar(me, vb, ra);
 #pragma unroll
             for (int c = 0; c < 5; ++c) acc[c] += ra[c];
-            if (send) {
-                double rbb[5];
-                reduce_bar(o, bb, rbb);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) s_buf[(F_MSG + c) * NODES + pn] = rbb[c];
-            }
-        };
-#pragma unroll
-        for (int r = 1; 2 * r < N; ++r) {
-            int b = il + r;
-            if (b >= N) b -= N;
-            if (tid < NODES) pair(b, true);
-            __syncthreads();
-            if (tid < NODES) {
-#pragma unroll
-                for (int c = 0; c < 5; ++c) acc[c] += s_buf[(F_MSG + c) * NODES + tid];
-            }
-            __syncthreads();
-        }
-        if constexpr (N % 2 == 0) {
-            // both nodes of the pair evaluate it; each keeps its own cotangent
-            if (tid < NODES) {
-                int b = il + N / 2;
-                if (b >= N) b -= N;
-                pair(b, false);
-            }
         }
         __syncthreads();
+    } else {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (tid < NODES) {
+                s_buf[(F_A + 0) * NODES + tid] = A[l][0];
+                s_buf[(F_A + 1) * NODES + tid] = A[l][1];
+                s_buf[(F_A + 2) * NODES + tid] = A[l][2];
+            }
+            __syncthreads();
+            const int il = idx[l];
+            const int st = stride[l];
+            auto pair = [&](int b, bool send) {
+                const int pn = tid + (b - il) * st;
+                Node o;
+                o.rho = s_buf[F_RHO * NODES + pn];
+                o.u1 = s_buf[F_U1 * NODES + pn];
+                o.u2 = s_buf[F_U2 * NODES + pn];
+                o.u3 = s_buf[F_U3 * NODES + pn];
+                o.beta = s_buf[F_B * NODES + pn];
+                o.lrho = s_buf[F_LR * NODES + pn];
+                o.lbeta = s_buf[F_LB * NODES + pn];
+                o.k = s_buf[F_K * NODES + pn];
+                const double n0 = A[l][0] + s_buf[(F_A + 0) * NODES + pn];
+                const double n1 = A[l][1] + s_buf[(F_A + 1) * NODES + pn];
+                const double n2 = A[l][2] + s_buf[(F_A + 2) * NODES + pn];
+                const double dab = s_D[il * N + b], dba = s_D[b * N + il];
+                double fb[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) fb[c] = -dab * rb[c] - dba * s_buf[(F_RB + c) * NODES + pn];
+                NodeBar ab, bb;
+                two_point_vjp<FLUX>(me, o, n0, n1, n2, gm1, fb, ab, bb);
+                double ra[5];
+                reduce_bar(me, ab, ra);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) acc[c] += ra[c];
+                if (send) {
+                    double rbb[5];
+                    reduce_bar(o, bb, rbb);
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) s_buf[(F_MSG + c) * NODES + pn] = rbb[c];
+                }
+            };
+#pragma unroll
+            for (int r = 1; 2 * r < N; ++r) {
+                int b = il + r;
+                if (b >= N) b -= N;
+                if (tid < NODES) pair(b, true);
+                __syncthreads();
+                if (tid < NODES) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[c] += s_buf[(F_MSG + c) * NODES + tid];
+                }
+                __syncthreads();
+            }
+            if constexpr (N % 2 == 0) {
+                // both nodes of the pair evaluate it; each keeps its own cotangent
+                if (tid < NODES) {
+                    int b = il + N / 2;
+                    if (b >= N) b -= N;
+                    pair(b, false);
+                }
+            }
+            __syncthreads();
+        }
     }
 
     // ---- interface SAT and dissipation (own and neighbour view) ----------------------------
@@ -1296,7 +1371,9 @@ template <int N, int EPW, bool OR>
 int launch_vjp_or(const VjpArgs &a, hipStream_t s) {
     switch (a.two_point) {
         case 0: return launch_vjp_f<N, EPW, OR, 0>(a, s);
+        case 1: return launch_vjp_f<N, EPW, OR, 1>(a, s);
         case 2: return launch_vjp_f<N, EPW, OR, 2>(a, s);
+        case 3: return launch_vjp_f<N, EPW, OR, 3>(a, s);
         default: return -1;
     }
 }

@@ -125,13 +125,3 @@ def test_vjp_full_size_dot_product():
     # the cotangent reaches at most two element layers beyond its support
     outside = np.setdiff1d(np.arange(prob.K), ring)
     assert np.all(qb[:, outside] == 0.0)
-
-
-def test_vjp_rejects_the_dc_and_central_forms():
-    require_gpu()
-    for tp in (1, 3):
-        c = Case(W.make_problem(p=2, E=2, L=2.0, A=0.1, mu=0.0, two_point=tp, seed=3, u_rms=0.3))
-        ps = P.ProblemSet([device_problem(c)])
-        q = to_dev(c.q)
-        with pytest.raises(P.SBPError):
-            ps.residual_vjp(q, torch.ones_like(q))
