@@ -453,7 +453,7 @@ int next_vjp_mark() {
 
 extern "C" {
 
-int sbp_version(void) { return 111; }
+int sbp_version(void) { return 112; }
 
 const char *sbp_error_string(int code) {
     switch (code) {
