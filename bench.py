@@ -520,8 +520,9 @@ def main():
         cpu_leg(args.workload, args.cpu_sample)
         return 0
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by element blocks across GPUs, which this build does not run)",
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
+              "runs each problem set on a single GPU (a multi-GPU run would shard element blocks "
+              "across GPUs and exchange face traces, which the library does not implement)",
               file=sys.stderr)
         return 2
 
