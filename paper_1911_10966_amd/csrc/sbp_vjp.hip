@@ -1232,114 +1232,132 @@ __device__ __forceinline__ void matrix_dissipation_vjp(const Node &a, const Node
 }
 
 // ------------------------------------------------------------------------------------------
-// Pass 4 (iface_diss = 2): the matrix interface dissipation, one thread per node; adds to qbar.
+// Pass 4 (iface_diss = 2): the matrix interface dissipation; adds to qbar.  One workgroup per
+// element, one thread per (face, face node) item: most nodes of small elements lie on a face, and
+// a per-node loop over directions would run three passes of the whole reverse sweep per wave.
 // Across an interior face the two sides' terms are -M(q_i, q_nu)/(2 w_end) and its negative (M is
 // odd in the exchange of the states and even in the sign of the normal), so the own node's
 // cotangent is (dM/dq_i)^T applied to -(rbar_i - rbar_nu)/(2 w_end).  A boundary ghost has no
 // cotangent of its own; a wall ghost is an image of the own state and is differentiated with it.
+// Each item leaves the cotangents of its node's (rho, U, beta) in an LDS slot; each node then adds
+// its (at most three) slots in direction order and maps them to conservative variables.
 // ------------------------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(256) k_vjp_md(const VjpArgs a) {
-    constexpr int N2 = N * N, N3 = N * N * N;
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.nodes) return;
-    const long long e = g / N3;
-    const int ln = (int)(g - e * N3);
-    const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
-    if (i1 != 0 && i1 != N - 1 && i2 != 0 && i2 != N - 1 && i3 != 0 && i3 != N - 1) return;
+__global__ void __launch_bounds__(NT_OF(6 * N * N)) k_vjp_md(const VjpArgs a) {
+    constexpr int N2 = N * N, N3 = N * N * N, ITEMS = 6 * N2;
+    constexpr int NT = NT_OF(ITEMS);
+    __shared__ double slot[5 * ITEMS];
+    const long long e = blockIdx.x;
     const long long nodes = a.nodes;
     const double gm1 = a.gamma - 1.0;
     const double isw = 1.0 / a.w_end;
-    double q[5], rb[5];
-    const double iJ = rcp(a.jac[g]);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        q[c] = a.q[c * nodes + g];
-        rb[c] = a.gbar[c * nodes + g] * iJ;
-    }
-    Node me;
-    double Pme;
-    bool ok;
-    primitives(q, gm1, me, Pme, ok);
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // cotangents of rho, U, beta
-#pragma unroll 1
-    for (int l = 0; l < 3; ++l) {
-        // (selects rather than indexed arrays: the loop is not unrolled)
-        const int il = l == 0 ? i1 : (l == 1 ? i2 : i3);
+    const int it = threadIdx.x;
+    if (it < ITEMS) {
+        const int f = it / N2, t = it - f * N2;
+        const int l = f >> 1, side = f & 1;
+        const int ta = t % N, tb = t / N;
+        const int il = side ? N - 1 : 0;
         const int st = l == 0 ? 1 : (l == 1 ? N : N2);
-        if (il != 0 && il != N - 1) continue;
-        const int side = (il == N - 1) ? 1 : 0;
-        const long long nb = a.nbr[e * 6 + 2 * l + side];
+        const int ln = l == 0 ? il + N * ta + N2 * tb : (l == 1 ? ta + N * il + N2 * tb : ta + N * tb + N2 * il);
+        const long long g = e * N3 + ln;
+        const long long nb = a.nbr[e * 6 + f];
         const int kind = face_kind(a, nb);
-        if (kind == FACE_INVALID) continue;  // flagged by the main pass
-        double Al[3], An[3], qn[5], cb[5];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) Al[m] = An[m] = a.metric[(3 * l + m) * nodes + g];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) cb[c] = -0.5 * isw * rb[c];
-        if (kind == FACE_INTERIOR) {
-            const int ta = l == 0 ? i2 : i1, tb = l == 2 ? i2 : i3;
-            const FaceLink k = face_link<N>(a, e, 2 * l + side, ta, tb, ln + (N - 1 - 2 * il) * st);
-            const long long pg = nb * N3 + k.lno;
-            const int lp = k.fp >> 1;
-#pragma unroll
-            for (int m = 0; m < 3; ++m) An[m] = k.sg * a.metric[(3 * lp + m) * nodes + pg];
-            const double iJn = rcp(a.jac[pg]);
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // cotangents of the node's rho, U, beta
+        if (kind != FACE_INVALID) {  // (an invalid face is flagged by the main pass)
+            double q[5], cb[5], Al[3], An[3], qn[5];
+            const double iJ = rcp(a.jac[g]);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
-                qn[c] = a.q[c * nodes + pg];
-                cb[c] += 0.5 * isw * a.gbar[c * nodes + pg] * iJn;
+                q[c] = a.q[c * nodes + g];
+                cb[c] = -0.5 * isw * a.gbar[c * nodes + g] * iJ;
             }
-        } else if (kind == FACE_DIRICHLET) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
-        } else {
-            // wall ghosts: the own state with the momentum reversed (no-slip) or reflected about
-            // the face (slip)
-            qn[0] = q[0];
-            qn[4] = q[4];
-            if (kind == FACE_WALL) {
-                qn[1] = -q[1]; qn[2] = -q[2]; qn[3] = -q[3];
+            for (int m = 0; m < 3; ++m) Al[m] = An[m] = a.metric[(3 * l + m) * nodes + g];
+            if (kind == FACE_INTERIOR) {
+                const FaceLink k = face_link<N>(a, e, f, ta, tb, ln + (N - 1 - 2 * il) * st);
+                const long long pg = nb * N3 + k.lno;
+                const int lp = k.fp >> 1;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) An[m] = k.sg * a.metric[(3 * lp + m) * nodes + pg];
+                const double iJn = rcp(a.jac[pg]);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    qn[c] = a.q[c * nodes + pg];
+                    cb[c] += 0.5 * isw * a.gbar[c * nodes + pg] * iJn;
+                }
+            } else if (kind == FACE_DIRICHLET) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) qn[c] = a.bc[c * nodes + g];
             } else {
-                const double mn = (q[1] * Al[0] + q[2] * Al[1] + q[3] * Al[2]) *
-                                  rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
+                // wall ghosts: the own state with the momentum reversed (no-slip) or reflected
+                // about the face (slip)
+                qn[0] = q[0];
+                qn[4] = q[4];
+                if (kind == FACE_WALL) {
+                    qn[1] = -q[1]; qn[2] = -q[2]; qn[3] = -q[3];
+                } else {
+                    const double mn = (q[1] * Al[0] + q[2] * Al[1] + q[3] * Al[2]) *
+                                      rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
 #pragma unroll
-                for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, Al[m], q[1 + m]);
+                    for (int m = 0; m < 3; ++m) qn[1 + m] = fma(-2.0 * mn, Al[m], q[1 + m]);
+                }
+            }
+            Node me, o;
+            double Pme, Pn;
+            bool ok;
+            primitives(q, gm1, me, Pme, ok);
+            primitives_nolog(qn, gm1, o, Pn);
+            o.lrho = log(o.rho);
+            o.lbeta = log(o.beta);
+            NodeBar ab, bb;
+            matrix_dissipation_vjp(me, o, 0.5 * (Al[0] + An[0]), 0.5 * (Al[1] + An[1]),
+                                   0.5 * (Al[2] + An[2]), a.gamma, a.R, cb, ab, bb);
+            reduce_bar(me, ab, acc);
+            if (kind == FACE_WALL || kind == FACE_SLIP) {
+                // the ghost's rho and beta are the own ones; its velocity the reversed or
+                // reflected one
+                double rg[5];
+                reduce_bar(o, bb, rg);
+                acc[0] += rg[0];
+                acc[4] += rg[4];
+                if (kind == FACE_WALL) {
+                    acc[1] -= rg[1]; acc[2] -= rg[2]; acc[3] -= rg[3];
+                } else {
+                    const double un = (rg[1] * Al[0] + rg[2] * Al[1] + rg[3] * Al[2]) *
+                                      rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) acc[1 + m] += rg[1 + m] - 2.0 * un * Al[m];
+                }
             }
         }
-        Node o;
-        double Pn;
-        primitives_nolog(qn, gm1, o, Pn);
-        o.lrho = log(o.rho);
-        o.lbeta = log(o.beta);
-        NodeBar ab, bb;
-        matrix_dissipation_vjp(me, o, 0.5 * (Al[0] + An[0]), 0.5 * (Al[1] + An[1]), 0.5 * (Al[2] + An[2]),
-                               a.gamma, a.R, cb, ab, bb);
-        double ra[5];
-        reduce_bar(me, ab, ra);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) acc[c] += ra[c];
-        if (kind == FACE_WALL || kind == FACE_SLIP) {
-            // the ghost's rho and beta are the own ones; its velocity the reversed or reflected one
-            double rg[5];
-            reduce_bar(o, bb, rg);
-            acc[0] += rg[0];
-            acc[4] += rg[4];
-            if (kind == FACE_WALL) {
-                acc[1] -= rg[1]; acc[2] -= rg[2]; acc[3] -= rg[3];
-            } else {
-                const double un = (rg[1] * Al[0] + rg[2] * Al[1] + rg[3] * Al[2]) *
-                                  rcp(Al[0] * Al[0] + Al[1] * Al[1] + Al[2] * Al[2]);
-#pragma unroll
-                for (int m = 0; m < 3; ++m) acc[1 + m] += rg[1 + m] - 2.0 * un * Al[m];
-            }
-        }
+        for (int c = 0; c < 5; ++c) slot[c * ITEMS + it] = acc[c];
     }
-    double ub[3] = {acc[1], acc[2], acc[3]};
-    double qb[5];
-    prim_vjp(q, gm1, a.R, acc[0], ub, acc[4], 0.0, 0.0, qb);
+    __syncthreads();
+    for (int ln = threadIdx.x; ln < N3; ln += NT) {
+        const int i1 = ln % N, i2 = (ln / N) % N, i3 = ln / N2;
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        bool any = false;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] += qb[c];
+        for (int l = 0; l < 3; ++l) {
+            const int il = l == 0 ? i1 : (l == 1 ? i2 : i3);
+            if (il != 0 && il != N - 1) continue;
+            any = true;
+            const int at = (2 * l + (il == N - 1 ? 1 : 0)) * N2 + tangential_index<N>(l, i1, i2, i3);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[c] += slot[c * ITEMS + at];
+        }
+        if (!any) continue;
+        const long long g = e * N3 + ln;
+        double q[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q[c] = a.q[c * nodes + g];
+        double ub[3] = {acc[1], acc[2], acc[3]};
+        double qb[5];
+        prim_vjp(q, gm1, a.R, acc[0], ub, acc[4], 0.0, 0.0, qb);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) a.qbar[c * nodes + g] += qb[c];
+    }
 }
 
 template <int N, int EPW, bool OR, int FLUX>
@@ -1361,7 +1379,7 @@ int launch_vjp_f(const VjpArgs &a, hipStream_t s) {
     }
     if (hipGetLastError() != hipSuccess) return -1;
     if (a.iface_diss == 2) {
-        hipLaunchKernelGGL((k_vjp_md<N>), dim3((unsigned)((a.nodes + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_vjp_md<N>), dim3((unsigned)a.K), dim3(NT_OF(6 * N * N)), 0, s, a);
         if (hipGetLastError() != hipSuccess) return -1;
     }
     return 0;
