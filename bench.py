@@ -71,7 +71,7 @@ def algorithmic_bytes(p, K, viscous):
 TRAFFIC = {"sha256": "f32098077683836208571f657512c15743e029da53ad064848b5b7bf82fcbf40",
            "workload": "ns_tgv_p4_e32",
            # bytes per launch by residual schedule index (degree 4)
-           "bytes": {0: 1313959688, 1: 1295677824, 2: 1036065104, 3: 1025955520, 4: 1313292464, 5: 1293528616, 6: 1274066942}}
+           "bytes": {0: 1313471008, 1: 1296047112, 2: 1036740304, 3: 1025980944, 4: 1313494904, 5: 1295059104, 6: 1274174944}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 
