@@ -194,9 +194,13 @@ def vjp_rate(P, W, dev, reps, iface_diss=None):
     ms_r = timed(lambda: ps.residual(q, out), reps)
     ms_v = timed(lambda: ps.residual_vjp(q, gb, out), reps)
     ps.status()
+    # algorithmic HBM bytes of a VJP: q, gbar, metrics and J read, qbar written (200 B per node)
+    vjp_bytes = prob.n_nodes * (BYTES_NODE + 40)
     return {"Mdof_vjp_per_s": round(prob.n_nodes / (ms_v * 1e-3) / 1e6, 1), "ms": round(ms_v, 4),
             "residual_ms": round(ms_r, 4), "vjp_over_residual_cost": round(ms_v / ms_r, 3),
-            "nodes": prob.n_nodes}
+            "nodes": prob.n_nodes,
+            "hbm_GBps_algorithmic": round(vjp_bytes / (ms_v * 1e-3) / 1e9, 1),
+            "hbm_frac": round(vjp_bytes / (ms_v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def mesh_variants_rate(P, W, dev, reps, E=16):
