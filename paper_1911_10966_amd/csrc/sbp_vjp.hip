@@ -513,13 +513,13 @@ k_vjp_visc(const VjpArgs a) {
     }
 }
 
-// Reverse of the interface terms (EC flux, dissipation, interior penalty) at one face node with
-// outward sign s, partner state qn with metric row An and 1/J iJn, and partner cotangent rbn (the
-// partner's own view of the same pair; zero for a boundary ghost).  BND: the partner is a boundary
-// ghost of kind `kind` (Dirichlet data is a constant; a wall ghost is the own state with the
-// momentum reversed or reflected, differentiated through the own state).  Accumulates the
-// cotangents of the own node's (rho, U, beta) in acc, of P and T, of q directly (qdir), and of the
-// entropy variables (wb).
+// Reverse of the interface terms (shared two-point flux, with the own-flux part for the DC form;
+// Lax-Friedrichs dissipation; interior penalty) at one face node with outward sign s, partner
+// state qn with metric row An and 1/J iJn, and partner cotangent rbn (the partner's own view of
+// the same pair; zero for a boundary ghost).  BND: the partner is a boundary ghost of kind `kind`
+// (Dirichlet data is a constant; a wall ghost is the own state with the momentum reversed or
+// reflected, differentiated through the own state).  Accumulates the cotangents of the own node's
+// (rho, U, beta) in acc, of P and T, of q directly (qdir), and of the entropy variables (wb).
 template <bool VISC, bool BND, int FLUX>
 __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, const double q[5],
                                               const double rb[5], const double Al[3], double iJ,
