@@ -501,6 +501,8 @@ def main():
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--kernel-reps", type=int, default=0,
                     help="extra profiled residual launches after the timed region")
+    ap.add_argument("--vjp", action="store_true",
+                    help="only the VJP of the adjoint workload (Lax-Friedrichs and matrix dissipation)")
     ap.add_argument("--cost-experiment", action="store_true",
                     help="run only the ES-C / SF-KG / DC cost comparison at 256^3 DOFs and print it")
     ap.add_argument("--robustness", action="store_true",
@@ -540,6 +542,11 @@ def main():
     torch.cuda.set_device(0)
     if args.cost_experiment:
         print(json.dumps({"cost_of_entropy_stability": cost_experiment(P, W, dev, 5)}), flush=True)
+        return 0
+    if args.vjp:
+        print(json.dumps({"vjp_p4_e16": vjp_rate(P, W, dev, 10),
+                          "vjp_matrix_dissipation_p4_e16": vjp_rate(P, W, dev, 10, iface_diss=2)}),
+              flush=True)
         return 0
     if args.mms:
         meshes = {1: (4, 8, 16, 32, 64), 2: (2, 4, 8, 16, 32), 3: (2, 4, 8, 16), 4: (2, 4, 8, 16),
