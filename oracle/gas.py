@@ -205,8 +205,19 @@ def contract(F, n):
 
 
 def sound_speed(q, gas: Gas):
+    """c = sqrt(gamma P / rho) (ideal gas)."""
     rho, u, P, T = primitives(q, gas)
     return np.sqrt(gas.gamma * P / rho)
+
+
+def max_wave_speed(q, n, gas: Gas):
+    """|U . n| + c |n|: the largest characteristic speed of the Euler flux contracted with the
+    (unnormalised) vector n, i.e. the spectral radius of d(F(q) . n)/dq.  This is the wave speed of
+    the local Lax-Friedrichs interface dissipation (absolute value decided on the real part)."""
+    rho, u, P, T = primitives(q, gas)
+    un = (u * n).sum(0)
+    aun = np.where(np.real(un) >= 0, un, -un)
+    return aun + sound_speed(q, gas) * np.sqrt((n * n).sum(0))
 
 
 def viscous_blocks(q, gas: Gas):

@@ -245,15 +245,7 @@ def inviscid_sat(q_all, metric_all, nbr, elems, sbp, prm: Params, bc=None, orien
         if prm.iface_diss == 2:
             sat = sat - G.matrix_dissipation(qi, qn, nbar, gas) / (2.0 * w_end)
         elif prm.iface_diss:
-            nn = np.sqrt((nbar * nbar).sum(0))
-
-            def speed(qx):
-                rho, u, P, T = G.primitives(qx, gas)
-                un = (u * nbar).sum(0)
-                aun = np.where(np.real(un) >= 0, un, -un)
-                return aun + G.sound_speed(qx, gas) * nn
-
-            li, ln = speed(qi), speed(qn)
+            li, ln = G.max_wave_speed(qi, nbar, gas), G.max_wave_speed(qn, nbar, gas)
             lam = np.where(np.real(li) >= np.real(ln), li, ln)
             sat = sat - (lam / (2.0 * w_end)) * (qi - qn)
         out[_index(out.ndim, own, l)] += sat
