@@ -148,9 +148,15 @@ size_t sbp_workspace_bytes(const sbp_problem *probs, int32_t n_prob);
 int sbp_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
                  void *ws, size_t ws_bytes, void *stream);
 
-/* Classical fourth-order Runge-Kutta steps with fixed time steps: q <- RK4(q, dt[b]) n_steps times.
+/* Classical fourth-order Runge-Kutta steps with fixed time steps: q <- RK4(q, dt[b]) n_steps times,
+ * k1 = f(q), k2 = f(q + dt/2 k1), k3 = f(q + dt/2 k2), k4 = f(q + dt k3),
+ * q <- q + dt/6 (k1 + 2 k2 + 2 k3 + k4), f the residual of sbp_residual.  The paper advances its
+ * semi-discretization with an adaptive fifth-order Dormand-Prince pair (numerical results section,
+ * time integration); this entry point instead takes the fixed steps dt the caller supplies, which
+ * is what a step of the paper's method costs without the error control.
  * q: device in/out, same layout as sbp_residual; dt: device [n_prob].  The four stages of a step are
- * recorded once into a HIP graph per (problem set, q, dt, workspace) and replayed. */
+ * recorded once into a HIP graph per (problem set, q, dt, workspace) and replayed; the graph and
+ * the launch plan stay cached until sbp_release(ws). */
 int sbp_rk_step(const sbp_problem *probs, int32_t n_prob, double *q, const double *dt,
                 int32_t n_steps, void *ws, size_t ws_bytes, void *stream);
 
@@ -191,10 +197,24 @@ int sbp_schedule_count(int32_t p);
 int sbp_set_schedule(const sbp_problem *probs, int32_t n_prob, void *ws, size_t ws_bytes, int32_t p,
                      int32_t variant);
 
-/* Waits for `stream`, then reports and clears the workspace's sticky device flags:
- * *flags = 0 when every state seen since the last call was physical, else SBP_ERR_NONPHYSICAL's
- * bit 1.  Returns SBP_ERR_NONPHYSICAL in that case, SBP_OK otherwise. */
+/* Waits for `stream`, then reports and clears the workspace's sticky device flags, which every
+ * residual, RK4 and VJP launch with this workspace may raise (the calls themselves do not read them
+ * back, so that they stay asynchronous):
+ *   *flags (host) receives the flag word: bit 0 (value 1) a non-physical state (rho <= 0, P <= 0 or
+ *   a non-finite value), bit 1 (value 2) a mesh error (a neighbour index outside [0, K) that names
+ *   no boundary kind, boundary data missing for a Dirichlet face, a slip wall on a viscous problem,
+ *   or an invalid face_orient entry); 0 when neither was seen since the last sbp_status call.
+ * Returns SBP_ERR_NONPHYSICAL if bit 0 is set, else SBP_ERR_MESH if bit 1 is set, else SBP_OK;
+ * SBP_ERR_ARG for a null ws or flags, SBP_ERR_HIP if the wait or the copy fails. */
 int sbp_status(void *ws, void *stream, int32_t *flags);
+
+/* Releases what the library caches for calls made with workspace `ws`: the launch plans (small
+ * device tables of the problem groups, made on the first call of a problem set) and the recorded
+ * RK4 graphs.  Call it before the workspace is freed or reused for another problem set; later calls
+ * with `ws` make new plans.  Waits for the whole device first (no cached plan or graph may be in
+ * use).  Returns the number of plans and graphs released (>= 0), SBP_ERR_ARG for a null ws or
+ * SBP_ERR_HIP if the wait fails. */
+int sbp_release(void *ws);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ SBP_BC_ADIABATIC_WALL = -3
 EXPORTED = ("sbp_version", "sbp_error_string", "sbp_lgl_operator", "sbp_metrics",
             "sbp_workspace_bytes", "sbp_residual", "sbp_rk_step", "sbp_residual_vjp",
             "sbp_profile_residual", "sbp_autotune", "sbp_schedule_count", "sbp_set_schedule",
-            "sbp_status")
+            "sbp_status", "sbp_release")
 
 
 class sbp_problem(ctypes.Structure):
@@ -76,6 +76,7 @@ def lib():
         L.sbp_rk_step.argtypes = [P, i32, vp, vp, i32, vp, sz, vp]
         L.sbp_residual_vjp.argtypes = [P, i32, vp, vp, vp, vp, sz, vp]
         L.sbp_status.argtypes = [vp, vp, ctypes.POINTER(i32)]
+        L.sbp_release.argtypes = [vp]
         L.sbp_schedule_count.argtypes = [i32]
         L.sbp_set_schedule.argtypes = [P, i32, vp, sz, i32, i32]
         L.sbp_autotune.argtypes = [P, i32, vp, vp, vp, sz, vp, i32, ctypes.POINTER(i32)]

@@ -3,6 +3,7 @@ provides device memory and the current stream only."""
 from __future__ import annotations
 
 import ctypes
+import sys
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -40,19 +41,22 @@ def _ptr(t: torch.Tensor):
 
 
 def _need(t: torch.Tensor, dtype, name):
-    if not t.is_cuda:
-        raise ValueError(f"{name} must be a device tensor")
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
 
 
 def metrics(p: int, coords: torch.Tensor):
     """Curl-form metric terms (9, nodes) and Jacobian (nodes,) from device coordinates (3, nodes)."""
+    N3 = (p + 1) ** 3
+    if coords.numel() == 0 or coords.numel() % (3 * N3) != 0:
+        raise ValueError(f"coords has {coords.numel()} entries, not a positive multiple of "
+                         f"3 (p+1)^3 = {3 * N3}")
     _need(coords, F64, "coords")
     nodes = coords.numel() // 3
-    N3 = (p + 1) ** 3
     K = nodes // N3
     metric = torch.empty((9, nodes), dtype=F64, device=coords.device)
     jac = torch.empty((nodes,), dtype=F64, device=coords.device)
@@ -86,23 +90,31 @@ class Problem:
     def nodes(self) -> int:
         return self.n_elem * (self.p + 1) ** 3
 
-    def c_struct(self) -> _lib.sbp_problem:
-        _need(self.nbr, torch.int32, "nbr")
-        _need(self.metric, F64, "metric")
-        _need(self.jac, F64, "jac")
-        extra = []
+    def arrays(self):
+        """(name, tensor, dtype, expected entries) of every device array of the problem."""
+        out = [("nbr", self.nbr, torch.int32, 6 * self.n_elem), ("metric", self.metric, F64, 9 * self.nodes),
+               ("jac", self.jac, F64, self.nodes)]
         for name in ("bc_state", "source"):
-            t = getattr(self, name)
-            if t is not None:
-                _need(t, F64, name)
-                if t.numel() != 5 * self.nodes:
-                    raise ValueError(f"{name} has {t.numel()} entries, expected {5 * self.nodes}")
-            extra.append(None if t is None else t.data_ptr())
+            if getattr(self, name) is not None:
+                out.append((name, getattr(self, name), F64, 5 * self.nodes))
         if self.face_orient is not None:
-            _need(self.face_orient, torch.int32, "face_orient")
-            if self.face_orient.numel() != 6 * self.n_elem:
-                raise ValueError(f"face_orient has {self.face_orient.numel()} entries, expected {6 * self.n_elem}")
-        extra.append(None if self.face_orient is None else self.face_orient.data_ptr())
+            out.append(("face_orient", self.face_orient, torch.int32, 6 * self.n_elem))
+        return out
+
+    def c_struct(self) -> _lib.sbp_problem:
+        """The C struct; raises ValueError for arrays of the wrong size, dtype, layout or device
+        (the library reads them through raw pointers and cannot check their extent)."""
+        if self.n_elem <= 0:
+            raise ValueError("n_elem must be positive")
+        arrs = self.arrays()
+        for name, t, dtype, n in arrs:
+            if t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+        for name, t, dtype, n in arrs:
+            _need(t, dtype, name)
+        if len({t.device for _, t, _, _ in arrs}) != 1:
+            raise ValueError("the arrays of a problem must be on one device")
+        extra = [None if t is None else t.data_ptr() for t in (self.bc_state, self.source, self.face_orient)]
         return _lib.sbp_problem(self.p, self.iface_diss, self.n_elem, self.nbr.data_ptr(),
                                 self.metric.data_ptr(), self.jac.data_ptr(), self.gamma, self.R,
                                 self.mu, self.Pr, self.eta, self.two_point, 0, *extra)
@@ -120,14 +132,37 @@ class ProblemSet:
         if self.ws_bytes == 0:
             raise _lib.SBPError(_lib.SBP_ERR_ARG, "sbp_workspace_bytes")
         dev = self.problems[0].metric.device
+        if any(p.metric.device != dev for p in self.problems):
+            raise ValueError("the problems of a set must be on one device")
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.total_nodes = sum(p.nodes for p in self.problems)
+
+    def release(self) -> int:
+        """Drops the library's cached launch plans and RK4 graphs of this set (they are made again
+        on the next call); returns how many were released.  Also done when the set is collected."""
+        ws = getattr(self, "ws", None)
+        if ws is None:
+            return 0
+        rc = lib().sbp_release(_ptr(ws))
+        if rc < 0:
+            check(rc, "sbp_release")
+        return rc
+
+    def __del__(self):
+        if sys.is_finalizing() or getattr(self, "ws", None) is None:
+            return
+        try:
+            self.release()
+        except Exception:  # pragma: no cover - runtime already torn down
+            pass
 
     def state_numel(self) -> int:
         return 5 * self.total_nodes
 
     def _check_state(self, t, name):
         _need(t, F64, name)
+        if t.device != self.ws.device:
+            raise ValueError(f"{name} is on {t.device}, the problem set on {self.ws.device}")
         if t.numel() != self.state_numel():
             raise ValueError(f"{name} has {t.numel()} entries, expected {self.state_numel()}")
 
@@ -168,6 +203,8 @@ class ProblemSet:
         """In-place classical RK4 steps; dt is a device float64 tensor with one entry per problem."""
         self._check_state(q, "q")
         _need(dt, F64, "dt")
+        if dt.device != self.ws.device:
+            raise ValueError(f"dt is on {dt.device}, the problem set on {self.ws.device}")
         if dt.numel() != self.n:
             raise ValueError("dt needs one entry per problem")
         check(lib().sbp_rk_step(self._arr, self.n, _ptr(q), _ptr(dt), n_steps, _ptr(self.ws),

@@ -223,6 +223,7 @@ struct GroupPlan {
 struct Plan {
     std::vector<GroupPlan> groups;
     int generation = 0;
+    const void *ws = nullptr;  // the workspace the plan was made for (sbp_release)
 };
 
 std::mutex g_plan_mu;
@@ -240,8 +241,93 @@ template <typename T>
 T *to_device(const std::vector<T> &v) {
     T *d = nullptr;
     if (hipMalloc(&d, sizeof(T) * v.size()) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
     return d;
+}
+
+void free_plan(Plan *plan) {
+    for (auto &g : plan->groups) {
+        if (g.d_probs) (void)hipFree(g.d_probs);
+        if (g.d_node_start) (void)hipFree(g.d_node_start);
+        for (auto &kv : g.d_block_start)
+            if (kv.second) (void)hipFree(kv.second);
+    }
+    delete plan;
+}
+
+// Problems grouped by launch kind (degree, viscous, flux, matrix dissipation, orientation table),
+// in order of first appearance; members in problem order.
+void group_problems(const sbp_problem *probs, int n, std::vector<GroupPlan> &groups) {
+    for (int b = 0; b < n; ++b) {
+        const bool visc = probs[b].mu > 0.0;
+        const bool md = probs[b].iface_diss == 2;
+        const bool orient = probs[b].face_orient != nullptr;
+        GroupPlan *gp = nullptr;
+        for (auto &g : groups)
+            if (g.p == probs[b].p && g.visc == visc && g.flux == probs[b].two_point && g.md == md &&
+                g.orient == orient)
+                gp = &g;
+        if (!gp) {
+            groups.emplace_back();
+            gp = &groups.back();
+            gp->p = probs[b].p;
+            gp->visc = visc;
+            gp->flux = probs[b].two_point;
+            gp->md = md;
+            gp->orient = orient;
+        }
+        gp->members.push_back(b);
+    }
+}
+
+// Device-table entry of problem b (state offset `off` doubles; viscous scratch at trace/thb).
+sbp::ProbDev prob_dev(const sbp_problem &pr, int b, long long off, double *trace, double *thb) {
+    sbp::ProbDev d{};
+    d.metric = pr.metric;
+    d.jac = pr.jac;
+    d.nbr = pr.nbr;
+    d.trace = pr.mu > 0.0 ? trace : nullptr;
+    d.thb = pr.mu > 0.0 ? thb : nullptr;
+    d.bc = pr.bc_state;
+    d.src = pr.source;
+    d.orient = pr.face_orient;
+    d.K = pr.n_elem;
+    d.nodes = nodes_of(pr);
+    d.off = off;
+    d.gamma = pr.gamma;
+    d.R = pr.R;
+    d.mu = pr.mu;
+    d.Pr = pr.Pr;
+    d.eta = pr.eta;
+    d.w_end = host_op(pr.p).w[0];
+    d.isw = 1.0 / d.w_end;
+    d.kap = pr.mu > 0.0 ? pr.mu * pr.gamma * pr.R / ((pr.gamma - 1.0) * pr.Pr) : 0.0;
+    d.iface_diss = pr.iface_diss;
+    d.two_point = pr.two_point;
+    d.dt_index = b;
+    return d;
+}
+
+// Prefix sums of the work units (elements, or node planes for the plane passes) per workgroup
+// tile of `epw` units over the members of a group.
+std::vector<long long> block_starts(const sbp_problem *probs, const GroupPlan &g, int epw) {
+    const long long per_elem = g.p >= sbp::kFirstPlaneP ? g.p + 1 : 1;
+    std::vector<long long> bs(1, 0);
+    for (int b : g.members) bs.push_back(bs.back() + (probs[b].n_elem * per_elem + epw - 1) / epw);
+    return bs;
+}
+
+std::vector<long long> state_offsets(const sbp_problem *probs, int n) {
+    std::vector<long long> off(n, 0);
+    long long acc = 0;
+    for (int b = 0; b < n; ++b) {
+        off[b] = acc;
+        acc += 5 * nodes_of(probs[b]);
+    }
+    return off;
 }
 
 Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
@@ -252,78 +338,34 @@ Plan *get_plan(const sbp_problem *probs, int n, char *ws, const Layout &L) {
     auto it = g_plans.find(key);
     if (it != g_plans.end()) return it->second;
     Plan *plan = new Plan();
-    std::vector<long long> off(n, 0);
-    long long acc = 0;
-    for (int b = 0; b < n; ++b) {
-        off[b] = acc;
-        acc += 5 * nodes_of(probs[b]);
-    }
-    for (int b = 0; b < n; ++b) {
-        const bool visc = probs[b].mu > 0.0;
-        const bool md = probs[b].iface_diss == 2;
-        const bool orient = probs[b].face_orient != nullptr;
-        GroupPlan *gp = nullptr;
-        for (auto &g : plan->groups)
-            if (g.p == probs[b].p && g.visc == visc && g.flux == probs[b].two_point && g.md == md &&
-                g.orient == orient)
-                gp = &g;
-        if (!gp) {
-            plan->groups.emplace_back();
-            gp = &plan->groups.back();
-            gp->p = probs[b].p;
-            gp->visc = visc;
-            gp->flux = probs[b].two_point;
-            gp->md = md;
-            gp->orient = orient;
-        }
-        gp->members.push_back(b);
-    }
+    plan->ws = ws;
+    const std::vector<long long> off = state_offsets(probs, n);
+    group_problems(probs, n, plan->groups);
     for (auto &g : plan->groups) {
         std::vector<sbp::ProbDev> host;
         std::vector<long long> ns(1, 0);
         for (int b : g.members) {
-            const sbp_problem &pr = probs[b];
-            sbp::ProbDev d{};
-            d.metric = pr.metric;
-            d.jac = pr.jac;
-            d.nbr = pr.nbr;
-            d.trace = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.trace[b]) : nullptr;
-            d.thb = pr.mu > 0.0 ? reinterpret_cast<double *>(ws + L.thb[b]) : nullptr;
-            d.bc = pr.bc_state;
-            d.src = pr.source;
-            d.orient = pr.face_orient;
-            d.K = pr.n_elem;
-            d.nodes = nodes_of(pr);
-            d.off = off[b];
-            d.gamma = pr.gamma;
-            d.R = pr.R;
-            d.mu = pr.mu;
-            d.Pr = pr.Pr;
-            d.eta = pr.eta;
-            d.w_end = host_op(pr.p).w[0];
-            d.isw = 1.0 / d.w_end;
-            d.kap = pr.mu > 0.0 ? pr.mu * pr.gamma * pr.R / ((pr.gamma - 1.0) * pr.Pr) : 0.0;
-            d.iface_diss = pr.iface_diss;
-            d.two_point = pr.two_point;
-            d.dt_index = b;
-            host.push_back(d);
-            ns.push_back(ns.back() + d.nodes);
+            host.push_back(prob_dev(probs[b], b, off[b], reinterpret_cast<double *>(ws + L.trace[b]),
+                                    reinterpret_cast<double *>(ws + L.thb[b])));
+            ns.push_back(ns.back() + host.back().nodes);
         }
         g.d_probs = to_device(host);
         g.d_node_start = to_device(ns);
         g.total_nodes = ns.back();
-        if (!g.d_probs || !g.d_node_start) return nullptr;
+        if (!g.d_probs || !g.d_node_start) {
+            free_plan(plan);
+            return nullptr;
+        }
         for (int v = 0; v < sbp::schedule_count(g.p); ++v) {
             const int epw = sbp::schedule_of(g.p, v).epw;
             if (g.d_block_start.count(epw)) continue;
-            // work units: elements, or node planes (N per element) for the plane passes
-            const long long per_elem = g.p >= sbp::kFirstPlaneP ? g.p + 1 : 1;
-            std::vector<long long> bs(1, 0);
-            for (int b : g.members)
-                bs.push_back(bs.back() + (probs[b].n_elem * per_elem + epw - 1) / epw);
+            const std::vector<long long> bs = block_starts(probs, g, epw);
             g.d_block_start[epw] = to_device(bs);
             g.total_blocks[epw] = bs.back();
-            if (!g.d_block_start[epw]) return nullptr;
+            if (!g.d_block_start[epw]) {
+                free_plan(plan);
+                return nullptr;
+            }
         }
     }
     plan->generation = ++g_generation;
@@ -453,7 +495,7 @@ int next_vjp_mark() {
 
 extern "C" {
 
-int sbp_version(void) { return 112; }
+int sbp_version(void) { return 113; }
 
 const char *sbp_error_string(int code) {
     switch (code) {
@@ -674,6 +716,38 @@ int sbp_set_schedule(const sbp_problem *probs, int32_t n_prob, void *ws, size_t 
         }
     plan->generation = ++g_generation;
     return SBP_OK;
+}
+
+int sbp_release(void *ws) {
+    if (ws == nullptr) return SBP_ERR_ARG;
+    // no launch recorded with these plans or graphs may still be running
+    if (hipDeviceSynchronize() != hipSuccess) return SBP_ERR_HIP;
+    int released = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+            if (it->first.ws == ws) {
+                (void)hipGraphExecDestroy(it->second);
+                it = g_graphs.erase(it);
+                ++released;
+            } else {
+                ++it;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (auto it = g_plans.begin(); it != g_plans.end();) {
+            if (it->second->ws == ws) {
+                free_plan(it->second);
+                it = g_plans.erase(it);
+                ++released;
+            } else {
+                ++it;
+            }
+        }
+    }
+    return released;
 }
 
 int sbp_schedule_count(int32_t p) { return (p < 1 || p > SBP_MAX_P) ? 0 : sbp::schedule_count(p); }

@@ -112,3 +112,42 @@ def test_empty_problem_list_is_rejected():
     assert L.sbp_residual(arr, 0, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
     assert L.sbp_residual(None, 1, 64, 128, 256, 1 << 20, None) == _lib.SBP_ERR_ARG
     assert L.sbp_workspace_bytes(arr, 0) == 0
+
+
+def test_release_rejects_a_null_workspace():
+    assert P.lib().sbp_release(None) == _lib.SBP_ERR_ARG
+
+
+def _host_problem(**over):
+    import torch
+    p, K = 2, 4
+    nodes = K * (p + 1) ** 3
+    f = dict(p=p, n_elem=K, nbr=torch.zeros(K, 6, dtype=torch.int32),
+             metric=torch.zeros(9, nodes, dtype=torch.float64), jac=torch.ones(nodes, dtype=torch.float64))
+    f.update(over)
+    return P.Problem(**f)
+
+
+@pytest.mark.parametrize("name,shape", [("nbr", (4, 5)), ("metric", (9, 107)), ("metric", (8, 108)),
+                                        ("jac", (107,)), ("bc_state", (5, 100)), ("source", (4, 108)),
+                                        ("face_orient", (3, 6))])
+def test_binding_rejects_arrays_of_the_wrong_size(name, shape):
+    """The library reads problem arrays through raw pointers, so the binding checks their extent."""
+    import torch
+    dtype = torch.int32 if name in ("nbr", "face_orient") else torch.float64
+    pr = _host_problem(**{name: torch.zeros(shape, dtype=dtype)})
+    with pytest.raises(ValueError, match="entries"):
+        pr.c_struct()
+
+
+def test_binding_rejects_host_arrays_and_bad_coordinate_counts():
+    import torch
+    with pytest.raises(ValueError, match="device tensor"):
+        _host_problem().c_struct()
+    with pytest.raises(ValueError, match="must be torch.int32"):
+        _host_problem(nbr=torch.zeros(4, 6, dtype=torch.int64)).c_struct()
+    with pytest.raises(ValueError, match="multiple"):
+        P.metrics(2, torch.zeros(3 * 27 + 3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="multiple"):
+        P.metrics(2, torch.zeros(0, dtype=torch.float64))
+
