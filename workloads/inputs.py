@@ -307,6 +307,22 @@ def state(prob: Problem, x: torch.Tensor) -> torch.Tensor:
     return torch.cat([rho[None], m, Et[None]]).contiguous()
 
 
+def jumped_state(prob: Problem, x: torch.Tensor, seed: int, amp: float = 0.5) -> torch.Tensor:
+    """The problem's state with density and pressure each multiplied, node by node, by an
+    independent factor exp(U[-amp, amp]) (velocity unchanged): neighbouring nodes then differ by up
+    to a factor e^(2 amp), so most two-point averages of rho and rho/(2P) are taken between far-apart
+    values.  Shape (5, K, N, N, N)."""
+    rho, u, p = primitive_state(prob, x)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fr = torch.as_tensor(np.exp(rng.uniform(-amp, amp, tuple(rho.shape))), dtype=F64, device=x.device)
+    fp = torch.as_tensor(np.exp(rng.uniform(-amp, amp, tuple(p.shape))), dtype=F64, device=x.device)
+    rho = rho * fr
+    p = p * fp
+    m = rho[None] * u
+    Et = p / (prob.gamma - 1.0) + 0.5 * rho * (u * u).sum(0)
+    return torch.cat([rho[None], m, Et[None]]).contiguous()
+
+
 def cfl_dt(prob: Problem, x: torch.Tensor, cfl: float = 0.25) -> float:
     """dt = cfl * (L/E) / ((p+1)^2 * max(|u| + c)) from the initial primitive fields."""
     rho, u, p = primitive_state(prob, x)
