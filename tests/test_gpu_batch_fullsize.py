@@ -1,6 +1,7 @@
 """The heterogeneous batch workload (256 periodic problems, p ~ U{2..8}, 2^3..12^3 elements) in the
-launch configuration the benchmark times: sampled problems and elements against the oracle, and
-conservation over 10 graph-replayed RK4 steps for every problem."""
+launch configuration the benchmark times: sampled problems and elements against the oracle,
+conservation over 10 graph-replayed RK4 steps for every problem, and the 10-step RK4 increments of
+five of its small problems against the oracle's RK4."""
 import numpy as np
 import pytest
 import torch
@@ -8,7 +9,7 @@ import torch
 import paper_1911_10966_amd as P
 import workloads as W
 from gpu_helpers import DEV, require_gpu
-from helpers import rel_err
+from helpers import rel_err, rk4_increment_check
 from oracle import geometry, operators, residual as R
 
 pytestmark = pytest.mark.gpu
@@ -84,3 +85,36 @@ def test_batch_rk4_ten_steps_conserves_every_problem():
     after = totals(qd)
     for (t0, s0), (t1, s1) in zip(before, after):
         assert torch.all((t1 - t0).abs() <= 1e-13 * s1)
+
+
+def test_batch_rk4_ten_steps_matches_oracle_on_small_problems():
+    """The whole batch advanced 10 RK4 steps in one graph-replayed call with the autotuned schedules;
+    problems 8, 44, 36, 5 and 70 (p = 3, 4, 6, 8, 2 on 2^3 or 3^3 elements) are checked against ten
+    oracle RK4 steps, increment by increment, to max(1e-12, 4 x the FP64 floor)."""
+    require_gpu()
+    picks = [8, 44, 36, 5, 70]
+    probs, dps, qd, dts, host = build_batch(oracle_for=picks)
+    ps = P.ProblemSet(dps)
+    ps.autotune(qd, reps=1)
+    q0 = qd.cpu().numpy()
+    ps.rk_step(qd, torch.tensor(dts, dtype=torch.float64, device=DEV), 10)
+    assert ps.status() == 0
+    q10 = qd.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([5 * d.nodes for d in dps])])
+    LD = np.longdouble
+    for b in picks:
+        pr = probs[b]
+        sbp, _ = host[b]
+        shape = (5, pr.K, pr.N, pr.N, pr.N)
+        metric = dps[b].metric.cpu().numpy().reshape((9,) + shape[1:])
+        jac = dps[b].jac.cpu().numpy().reshape(shape[1:])
+        nbr = W.neighbours(pr.E)
+        prm = R.Params.of(pr)
+        sbp_ld = operators.SBP1D(pr.p, LD)
+        m_ld, j_ld = metric.astype(LD), jac.astype(LD)
+        f = lambda y: R.residual(y, metric, jac, nbr, sbp, prm)  # noqa: E731
+        f_ld = lambda y: R.residual(y, m_ld, j_ld, nbr, sbp_ld, prm)  # noqa: E731
+        err, bar = rk4_increment_check(f, f_ld, q0[offs[b]:offs[b + 1]].reshape(shape), dts[b], 10,
+                                       q10[offs[b]:offs[b + 1]].reshape(shape))
+        print(f"  problem {b}: p={pr.p} E={pr.E} 10-step increment err {err:.2e} bar {bar:.1e}")
+        assert err < bar

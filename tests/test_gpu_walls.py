@@ -11,7 +11,7 @@ import paper_1911_10966_amd as P
 import workloads as W
 from workloads import mms
 from gpu_helpers import DEV, device_problem, from_dev, require_gpu, to_dev
-from helpers import Case, rel_err
+from helpers import Case, rel_err, rk4_increment_check
 from oracle import operators, residual as R
 
 pytestmark = pytest.mark.gpu
@@ -34,6 +34,13 @@ def _tol(c, q, ref):
                         operators.SBP1D(c.prob.p, LD), c.prm,
                         bc=None if c.bc is None else c.bc.astype(LD))
     return max(TOL, 4.0 * rel_err(ref, ref_ld))
+
+
+def _rhs(c, dtype=np.float64):
+    """The oracle residual of case c as a function of the state, in `dtype` arithmetic."""
+    m, j, sbp = c.metric.astype(dtype), c.jac.astype(dtype), operators.SBP1D(c.prob.p, dtype)
+    bc = None if c.bc is None else c.bc.astype(dtype)
+    return lambda y: R.residual(y, m, j, c.nbr, sbp, c.prm, bc=bc)
 
 
 def _dev_problem(c):
@@ -84,11 +91,11 @@ def test_wall_rk4_step_in_a_batch_with_a_periodic_problem():
     assert ps.status() == 0
     out = qd.cpu().numpy()
     n = qw.size
-    fw = lambda y: R.residual(y, cw.metric, cw.jac, cw.nbr, cw.sbp, cw.prm)  # noqa: E731
-    refw = R.rk4_step(fw, R.rk4_step(fw, qw, 2e-3), 2e-3)
-    refp = R.rk4_step(cp.residual, R.rk4_step(cp.residual, qp, 3e-3), 3e-3)
-    assert rel_err(out[:n].reshape(qw.shape) - qw, refw - qw) < 1e-10
-    assert rel_err(out[n:].reshape(qp.shape) - qp, refp - qp) < 1e-10
+    cp.bc = None
+    for c, q, dt, got in ((cw, qw, 2e-3, out[:n]), (cp, qp, 3e-3, out[n:])):
+        err, bar = rk4_increment_check(_rhs(c), _rhs(c, np.longdouble), q, dt, 2, got.reshape(q.shape))
+        print(f"  2-step RK4 increment err {err:.2e} bar {bar:.1e}")
+        assert err < bar
 
 
 @pytest.mark.parametrize("p,E", [(4, 16), (7, 8)])
@@ -111,7 +118,12 @@ def test_channel_conserves_mass_and_energy_at_size(p, E):
     rng = np.random.Generator(np.random.PCG64(p))
     elems = np.sort(rng.choice(prob.K, size=24, replace=False))
     ref = R.residual(q, c.metric, c.jac, c.nbr, c.sbp, c.prm, elems=elems)
-    assert rel_err(out[:, elems], ref) < 1e-11
+    LD = np.longdouble
+    ref_ld = R.residual(q.astype(LD), c.metric.astype(LD), c.jac.astype(LD), c.nbr,
+                        operators.SBP1D(p, LD), c.prm, elems=elems)
+    err, bar = rel_err(out[:, elems], ref_ld), max(TOL, 4.0 * rel_err(ref, ref_ld))
+    print(f"  sampled elements at size: err {err:.2e} bar {bar:.1e}")
+    assert err < bar
 
 
 def test_channel_manufactured_solution_residual_matches_oracle():
