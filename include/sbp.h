@@ -47,6 +47,7 @@ extern "C" {
 #define SBP_ERR_NONPHYSICAL (-4) /* reported by sbp_status: rho <= 0, P <= 0 or non-finite    */
 #define SBP_ERR_HIP (-5)         /* a HIP runtime call failed                                  */
 #define SBP_ERR_WORKSPACE (-6)   /* workspace missing or smaller than sbp_workspace_bytes()    */
+#define SBP_ERR_SCRATCH (-7)     /* problem set exceeds SBP_NOALLOC_SCRATCH_BYTES              */
 
 #define SBP_MAX_P 15      /* degrees 1..8 run one workgroup per element tile; 9..15 (the cost */
                          /* study of the Taylor-Green section goes up to p = 15) run as      */
@@ -188,6 +189,26 @@ int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double 
  * output.  chosen: optional host [n_prob] receiving the schedule index of each problem's group. */
 int sbp_autotune(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt, void *ws,
                  size_t ws_bytes, void *stream, int32_t reps, int32_t *chosen);
+
+/* Allocation-free residual, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the result of sbp_residual with the
+ * default schedule, computed by the same kernels, with no caller workspace and no allocation.  The
+ * viscous face traces, the plane passes' scratch and the small device tables live in one
+ * library-owned device array of SBP_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends;
+ * its address is looked up, and the collocation-derivative tables written into it, on the first
+ * call on each device (that call waits for `stream` once).
+ * probs, n_prob (1..SBP_NOALLOC_MAX_PROBLEMS), q, dqdt, stream: as in sbp_residual.
+ * status: device int32 owned by the caller; the launches OR the flag bits of sbp_status() into it
+ * (bit 0 non-physical state, bit 1 mesh error) and never clear it: the caller zeroes it.
+ * Needs, per viscous problem, 192 N^2 K bytes of face traces plus, for p >= 9, 128 N^3 K bytes of
+ * per-node scratch (each rounded up to 256 B), all within SBP_NOALLOC_SCRATCH_BYTES less 64 KiB;
+ * a larger set returns SBP_ERR_SCRATCH before any device work.  Every call on a GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other streams, other threads) race and give
+ * wrong results; serialize them. */
+#define SBP_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define SBP_NOALLOC_MAX_PROBLEMS 16
+int sbp_residual_noalloc(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
+                         int32_t *status, void *stream);
 
 /* Number of residual schedules available for degree p (0 if p is out of range). */
 int sbp_schedule_count(int32_t p);

@@ -13,6 +13,9 @@ SBP_ERR_MESH = -3
 SBP_ERR_NONPHYSICAL = -4
 SBP_ERR_HIP = -5
 SBP_ERR_WORKSPACE = -6
+SBP_ERR_SCRATCH = -7
+SBP_NOALLOC_SCRATCH_BYTES = 64 << 20
+SBP_NOALLOC_MAX_PROBLEMS = 16
 SBP_MAX_P = 15
 SBP_MAX_VJP_P = 8
 SBP_BC_DIRICHLET = -1
@@ -22,7 +25,7 @@ SBP_BC_ADIABATIC_WALL = -3
 EXPORTED = ("sbp_version", "sbp_error_string", "sbp_lgl_operator", "sbp_metrics",
             "sbp_workspace_bytes", "sbp_residual", "sbp_rk_step", "sbp_residual_vjp",
             "sbp_profile_residual", "sbp_autotune", "sbp_schedule_count", "sbp_set_schedule",
-            "sbp_status", "sbp_release")
+            "sbp_status", "sbp_release", "sbp_residual_noalloc")
 
 
 class sbp_problem(ctypes.Structure):
@@ -77,6 +80,7 @@ def lib():
         L.sbp_residual_vjp.argtypes = [P, i32, vp, vp, vp, vp, sz, vp]
         L.sbp_status.argtypes = [vp, vp, ctypes.POINTER(i32)]
         L.sbp_release.argtypes = [vp]
+        L.sbp_residual_noalloc.argtypes = [P, i32, vp, vp, vp, vp]
         L.sbp_schedule_count.argtypes = [i32]
         L.sbp_set_schedule.argtypes = [P, i32, vp, sz, i32, i32]
         L.sbp_autotune.argtypes = [P, i32, vp, vp, vp, sz, vp, i32, ctypes.POINTER(i32)]

@@ -175,6 +175,22 @@ class ProblemSet:
                                  _stream()), "sbp_residual")
         return out
 
+    def residual_noalloc(self, q: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         status: Optional[torch.Tensor] = None):
+        """The residual through sbp_residual_noalloc: no workspace (the library's own device scratch
+        instead) and no allocation inside the call.  ``status`` is a device int32 tensor of one
+        entry that receives the flag bits (zeroed here if not given).  Returns (out, status)."""
+        self._check_state(q, "q")
+        if out is None:
+            out = torch.empty_like(q)
+        self._check_state(out, "out")
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=q.device)
+        _need(status, torch.int32, "status")
+        check(lib().sbp_residual_noalloc(self._arr, self.n, _ptr(q), _ptr(out), _ptr(status), _stream()),
+              "sbp_residual_noalloc")
+        return out, status
+
     def profile_residual(self, q: torch.Tensor, out: torch.Tensor) -> float:
         """Runs the residual once and returns the main kernel's duration in ms (HIP events)."""
         self._check_state(q, "q")

@@ -506,6 +506,8 @@ const char *sbp_error_string(int code) {
         case SBP_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, P <= 0 or non-finite)";
         case SBP_ERR_HIP: return "HIP runtime error";
         case SBP_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case SBP_ERR_SCRATCH:
+            return "problem set too large for the library-owned scratch of sbp_residual_noalloc";
         default: return "unknown error";
     }
 }
@@ -748,6 +750,98 @@ int sbp_release(void *ws) {
         }
     }
     return released;
+}
+
+int sbp_residual_noalloc(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
+                         int32_t *status, void *stream) {
+    static_assert(SBP_NOALLOC_SCRATCH_BYTES == sbp::kNoallocScratchBytes, "scratch size");
+    if (probs == nullptr || n_prob < 1 || n_prob > SBP_NOALLOC_MAX_PROBLEMS) return SBP_ERR_ARG;
+    for (int b = 0; b < n_prob; ++b) {
+        const int rc = check_problem(probs[b]);
+        if (rc != SBP_OK) return rc;
+    }
+    if (!aligned8(q) || !aligned8(dqdt) || q == dqdt || status == nullptr ||
+        (reinterpret_cast<uintptr_t>(status) % 4) != 0)
+        return SBP_ERR_ARG;
+    // Scratch layout: [derivative tables, p = 0..15 | group tables | per viscous problem: face
+    // traces, then (p >= 9) the plane passes' per-node scratch].  Checked before any device work.
+    constexpr size_t kDBytes = sizeof(double) * 256 * (kMaxOpP + 1);
+    constexpr size_t kTableBytes = size_t(32) << 10;
+    std::vector<size_t> trace(n_prob, 0), aux(n_prob, 0);
+    size_t off = kDBytes + kTableBytes;
+    for (int b = 0; b < n_prob; ++b) {
+        const sbp_problem &pr = probs[b];
+        if (!(pr.mu > 0.0)) continue;
+        const size_t N = pr.p + 1;
+        trace[b] = off;
+        off += align_up(sizeof(double) * (size_t)pr.n_elem * 6 * 4 * N * N);
+        if (pr.p >= sbp::kFirstPlaneP) {
+            aux[b] = off;
+            off += align_up(sizeof(double) * 16 * (size_t)nodes_of(pr));
+        }
+    }
+    if (off > SBP_NOALLOC_SCRATCH_BYTES) return SBP_ERR_SCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    static const std::vector<double> dtab = [] {
+        std::vector<double> t(256 * (kMaxOpP + 1), 0.0);
+        for (int pp = 1; pp <= kMaxOpP; ++pp)
+            std::memcpy(t.data() + 256 * pp, host_op(pp).D, sizeof(double) * (pp + 1) * (pp + 1));
+        return t;
+    }();
+    char *scr = nullptr;
+    if (sbp::noalloc_scratch(dtab.data(), (long long)dtab.size(), s, &scr) != 0) return SBP_ERR_HIP;
+    // group tables packed into 8-byte words, uploaded through kernel arguments
+    std::vector<GroupPlan> groups;
+    group_problems(probs, n_prob, groups);
+    const std::vector<long long> soff = state_offsets(probs, n_prob);
+    std::vector<unsigned long long> words;
+    auto put = [&words](const void *data, size_t bytes) {
+        const size_t at = words.size();
+        words.resize(at + (bytes + 7) / 8, 0ull);
+        std::memcpy(words.data() + at, data, bytes);
+        return at * 8;
+    };
+    struct Where {
+        size_t probs, ns, bs;
+    };
+    std::vector<Where> where;
+    for (auto &g : groups) {
+        std::vector<sbp::ProbDev> host;
+        std::vector<long long> ns(1, 0);
+        for (int b : g.members) {
+            host.push_back(prob_dev(probs[b], b, soff[b], reinterpret_cast<double *>(scr + trace[b]),
+                                    reinterpret_cast<double *>(scr + aux[b])));
+            ns.push_back(ns.back() + host.back().nodes);
+        }
+        const std::vector<long long> bs = block_starts(probs, g, sbp::schedule_of(g.p, 0).epw);
+        g.total_nodes = ns.back();
+        g.total_blocks[sbp::schedule_of(g.p, 0).epw] = bs.back();
+        Where w;
+        w.probs = put(host.data(), sizeof(sbp::ProbDev) * host.size());
+        w.ns = put(ns.data(), sizeof(long long) * ns.size());
+        w.bs = put(bs.data(), sizeof(long long) * bs.size());
+        where.push_back(w);
+    }
+    if (words.size() * 8 > kTableBytes) return SBP_ERR_ARG;  // not reached with <= 16 problems
+    char *tab = scr + kDBytes;
+    if (sbp::fill_words(tab, words.data(), (long long)words.size(), s) != 0) return SBP_ERR_HIP;
+    for (size_t i = 0; i < groups.size(); ++i) {
+        const GroupPlan &g = groups[i];
+        sbp::GroupArgs a{};
+        a.probs = reinterpret_cast<const sbp::ProbDev *>(tab + where[i].probs);
+        a.node_start = reinterpret_cast<const long long *>(tab + where[i].ns);
+        a.block_start = reinterpret_cast<const long long *>(tab + where[i].bs);
+        a.n = (int)g.members.size();
+        a.total_blocks = g.total_blocks.at(sbp::schedule_of(g.p, 0).epw);
+        a.total_nodes = g.total_nodes;
+        a.q = q;
+        a.out = dqdt;
+        a.status = status;
+        a.D = reinterpret_cast<const double *>(scr) + 256 * g.p;
+        if (sbp::launch_group_residual(g.p, g.visc, g.flux, g.md, g.orient, 0, a, s, true) != 0)
+            return SBP_ERR_HIP;
+    }
+    return SBP_OK;
 }
 
 int sbp_schedule_count(int32_t p) { return (p < 1 || p > SBP_MAX_P) ? 0 : sbp::schedule_count(p); }

@@ -113,6 +113,15 @@ int launch_metrics_big(int p, long long K, const double *x, double *metric, doub
 
 
 
+// Library-owned scratch of the allocation-free residual (sbp_noalloc.hip): bytes of the device
+// array, words per table-upload launch (carried in kernel arguments), the upload itself, and the
+// per-device address of the array (set up on the first call on a device, which also writes the
+// collocation-derivative tables d_tables[n_words] at its start and waits for stream s).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kFillWords = 256;
+int fill_words(void *dst, const unsigned long long *src, long long n, hipStream_t s);
+int noalloc_scratch(const double *d_tables, long long n_words, hipStream_t s, char **ptr);
+
 // Optional event timing of the main residual kernel (see sbp_profile in the C ABI).
 struct KernelTimer {
     bool enabled = false;

@@ -151,3 +151,21 @@ def test_binding_rejects_host_arrays_and_bad_coordinate_counts():
     with pytest.raises(ValueError, match="multiple"):
         P.metrics(2, torch.zeros(0, dtype=torch.float64))
 
+
+def test_noalloc_rejects_oversize_sets_and_bad_arguments_on_host():
+    """sbp_residual_noalloc checks sizes against its fixed scratch before any device work."""
+    L = P.lib()
+    # viscous p = 4 on 100^3 elements: 4.8 GB of face traces, far beyond the scratch
+    big = _prob(p=4, n_elem=100 ** 3, mu=1e-3)
+    assert L.sbp_residual_noalloc(big, 1, 64, 128, 256, None) == _lib.SBP_ERR_SCRATCH
+    assert P.lib().sbp_error_string(_lib.SBP_ERR_SCRATCH).decode().startswith("problem set too large")
+    # the limit is the scratch size: 1 + (64 MiB - 64 KiB) // (192 N^2) elements of p = 4 do not fit
+    limit = ((_lib.SBP_NOALLOC_SCRATCH_BYTES - (64 << 10)) // (192 * 25)) + 1
+    assert L.sbp_residual_noalloc(_prob(p=4, n_elem=limit, mu=1e-3), 1, 64, 128, 256, None) == _lib.SBP_ERR_SCRATCH
+    ok = _prob()
+    assert L.sbp_residual_noalloc(ok, 0, 64, 128, 256, None) == _lib.SBP_ERR_ARG
+    many = (_lib.sbp_problem * (_lib.SBP_NOALLOC_MAX_PROBLEMS + 1))(*([ok[0]] * (_lib.SBP_NOALLOC_MAX_PROBLEMS + 1)))
+    assert L.sbp_residual_noalloc(many, _lib.SBP_NOALLOC_MAX_PROBLEMS + 1, 64, 128, 256, None) == _lib.SBP_ERR_ARG
+    assert L.sbp_residual_noalloc(ok, 1, 64, 128, None, None) == _lib.SBP_ERR_ARG      # no status word
+    assert L.sbp_residual_noalloc(ok, 1, 64, 64, 256, None) == _lib.SBP_ERR_ARG        # aliasing output
+    assert L.sbp_residual_noalloc(_prob(p=16), 1, 64, 128, 256, None) == _lib.SBP_ERR_DEGREE
