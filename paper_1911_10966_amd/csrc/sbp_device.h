@@ -22,28 +22,52 @@ __device__ __forceinline__ double rcp(double x) {
     return fma(r, e, r);
 }
 
+// Square root of a strictly positive, normal operand (a metric norm, a sound speed squared): the
+// hardware reciprocal square root refined by Goldschmidt's iteration and two Newton corrections
+// (about 1 ulp), without the scaling and special-case handling of the general square root.
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
+// A polynomial coefficient held in scalar registers: the empty asm statement makes the value opaque
+// to constant folding, so each Horner step below is one v_fma_f64 with a scalar addend (as an
+// immediate the compiler copies every coefficient into vector registers, two extra vector moves
+// per step).
+__device__ __forceinline__ double sreg(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
 // With z = (a-b)/(a+b) and u = z^2:  log(a/b) = 2 artanh z = 2 z F(u),  F(u) = sum_k u^k/(2k+1),
 // so the logarithmic mean is (a+b)/(2 F(u)) and its inverse 2 F(u)/(a+b).  For u < 1e-2 the
 // series below (F through u^7, G = 1/F through u^7) are accurate to < 1e-17 relative.
 __device__ __forceinline__ double series_F(double u) {
-    double r = 1.0 / 15.0;
-    r = fma(r, u, 1.0 / 13.0);
-    r = fma(r, u, 1.0 / 11.0);
-    r = fma(r, u, 1.0 / 9.0);
-    r = fma(r, u, 1.0 / 7.0);
-    r = fma(r, u, 1.0 / 5.0);
-    r = fma(r, u, 1.0 / 3.0);
+    double r = sreg(1.0 / 15.0);
+    r = fma(r, u, sreg(1.0 / 13.0));
+    r = fma(r, u, sreg(1.0 / 11.0));
+    r = fma(r, u, sreg(1.0 / 9.0));
+    r = fma(r, u, sreg(1.0 / 7.0));
+    r = fma(r, u, sreg(1.0 / 5.0));
+    r = fma(r, u, sreg(1.0 / 3.0));
     return fma(r, u, 1.0);
 }
 __device__ __forceinline__ double series_G(double u) {
     // coefficients of 1/F(u): g_k = -sum_{i=1..k} g_{k-i}/(2i+1), g_0 = 1
-    double r = -25865068.0 / 1915538625.0;
-    r = fma(r, u, -10719068.0 / 638512875.0);
-    r = fma(r, u, -10196.0 / 467775.0);
-    r = fma(r, u, -428.0 / 14175.0);
-    r = fma(r, u, -44.0 / 945.0);
-    r = fma(r, u, -4.0 / 45.0);
-    r = fma(r, u, -1.0 / 3.0);
+    double r = sreg(-25865068.0 / 1915538625.0);
+    r = fma(r, u, sreg(-10719068.0 / 638512875.0));
+    r = fma(r, u, sreg(-10196.0 / 467775.0));
+    r = fma(r, u, sreg(-428.0 / 14175.0));
+    r = fma(r, u, sreg(-44.0 / 945.0));
+    r = fma(r, u, sreg(-4.0 / 45.0));
+    r = fma(r, u, sreg(-1.0 / 3.0));
     return fma(r, u, 1.0);
 }
 
@@ -68,10 +92,11 @@ __device__ __forceinline__ void primitives(const double q[5], double gm1, Node &
     n.lbeta = ok ? log(n.beta) : 0.0;
 }
 
-// Primitives of a neighbour node without the logarithms (see flux_n<FLUX, true>).
-__device__ __forceinline__ void primitives_nolog(const double q[5], double gm1, Node &n, double &P) {
+// Primitives of a neighbour node without the logarithms (see flux_n<FLUX, true>); ir = 1/rho.
+__device__ __forceinline__ void primitives_nolog(const double q[5], double gm1, Node &n, double &P,
+                                                 double &ir) {
     n.rho = q[0];
-    const double ir = rcp(q[0]);
+    ir = rcp(q[0]);
     n.u1 = q[1] * ir;
     n.u2 = q[2] * ir;
     n.u3 = q[3] * ir;
@@ -80,6 +105,10 @@ __device__ __forceinline__ void primitives_nolog(const double q[5], double gm1, 
     n.beta = 0.5 * q[0] * rcp(P);
     n.lrho = 0.0;
     n.lbeta = 0.0;
+}
+__device__ __forceinline__ void primitives_nolog(const double q[5], double gm1, Node &n, double &P) {
+    double ir;
+    primitives_nolog(q, gm1, n, P, ir);
 }
 
 // Nodal inviscid flux (eq. ns_iflux) contracted with (n0, n1, n2): [rho U_n, rho U_n U + P n,
@@ -265,11 +294,11 @@ __device__ __forceinline__ void matrix_dissipation(const Node &a, const Node &b,
     const double zb = db * isb, ub_ = zb * zb;
     const double ibeta_hat = ub_ < LOGMEAN_U ? 2.0 * isb * series_F(ub_) : (a.lbeta - b.lbeta) * rcp(db);
     const double p_hat = 0.5 * sr * isb;  // rho_bar / (2 beta_bar)
-    const double a_hat = sqrt(gamma * p_hat * rcp(rho_hat));
+    const double a_hat = sqrt_pos(gamma * p_hat * rcp(rho_hat));
     const double u1 = 0.5 * (a.u1 + b.u1), u2 = 0.5 * (a.u2 + b.u2), u3 = 0.5 * (a.u3 + b.u3);
     const double ubsq = u1 * u1 + u2 * u2 + u3 * u3;
     const double h_hat = 0.5 * gamma / gm1 * ibeta_hat + ubsq - 0.25 * (a.k + b.k);
-    const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    const double nn = sqrt_pos(n0 * n0 + n1 * n1 + n2 * n2);
     const double inn = rcp(nn);
     const double e0 = n0 * inn, e1 = n1 * inn, e2 = n2 * inn;
     const double vn = u1 * e0 + u2 * e1 + u3 * e2;
@@ -431,7 +460,7 @@ __device__ __forceinline__ FaceOwn face_own(const ResArgs &a, const Node &m, dou
     FaceOwn o;
     o.m = m;
     o.P = P;
-    o.c = sqrt(a.gamma * P / m.rho);
+    o.c = sqrt_pos(a.gamma * P * rcp(m.rho));
     o.T = rcp(2.0 * a.R * m.beta);
     o.iJ = iJ;
     o.q = q;
@@ -449,8 +478,8 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
     const double *qn = nb.q;
     const double An0 = nb.A[0], An1 = nb.A[1], An2 = nb.A[2];
     Node o;
-    double Pn;
-    primitives_nolog(qn, gm1, o, Pn);
+    double Pn, irn;
+    primitives_nolog(qn, gm1, o, Pn, irn);
     const double n0 = 0.5 * (Ai[0] + An0), n1 = 0.5 * (Ai[1] + An1), n2 = 0.5 * (Ai[2] + An2);
     double f[5];
     flux_n<FLUX, true>(mi, o, n0, n1, n2, gm1, f);
@@ -473,9 +502,9 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
 #pragma unroll
         for (int c = 0; c < 5; ++c) v[c] = fma(cf, md[c], v[c]);
     } else if (a.iface_diss) {
-        const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double nn = sqrt_pos(n0 * n0 + n1 * n1 + n2 * n2);
         const double li = fabs(mi.u1 * n0 + mi.u2 * n1 + mi.u3 * n2) + ow.c * nn;
-        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
+        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt_pos(a.gamma * Pn * irn) * nn;
         const double cf = -0.5 * fmax(li, lo) * isw;
 #pragma unroll
         for (int c = 0; c < 5; ++c) v[c] = fma(cf, qi[c] - qn[c], v[c]);

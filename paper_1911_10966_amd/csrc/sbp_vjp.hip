@@ -21,22 +21,22 @@ namespace sbp {
 namespace {
 
 __device__ __forceinline__ double series_Fp(double u) {  // dF/du
-    double r = 7.0 / 15.0;
-    r = fma(r, u, 6.0 / 13.0);
-    r = fma(r, u, 5.0 / 11.0);
-    r = fma(r, u, 4.0 / 9.0);
-    r = fma(r, u, 3.0 / 7.0);
-    r = fma(r, u, 2.0 / 5.0);
-    return fma(r, u, 1.0 / 3.0);
+    double r = sreg(7.0 / 15.0);
+    r = fma(r, u, sreg(6.0 / 13.0));
+    r = fma(r, u, sreg(5.0 / 11.0));
+    r = fma(r, u, sreg(4.0 / 9.0));
+    r = fma(r, u, sreg(3.0 / 7.0));
+    r = fma(r, u, sreg(2.0 / 5.0));
+    return fma(r, u, sreg(1.0 / 3.0));
 }
 __device__ __forceinline__ double series_Gp(double u) {  // dG/du
-    double r = 7.0 * (-25865068.0 / 1915538625.0);
-    r = fma(r, u, 6.0 * (-10719068.0 / 638512875.0));
-    r = fma(r, u, 5.0 * (-10196.0 / 467775.0));
-    r = fma(r, u, 4.0 * (-428.0 / 14175.0));
-    r = fma(r, u, 3.0 * (-44.0 / 945.0));
-    r = fma(r, u, 2.0 * (-4.0 / 45.0));
-    return fma(r, u, -1.0 / 3.0);
+    double r = sreg(7.0 * (-25865068.0 / 1915538625.0));
+    r = fma(r, u, sreg(6.0 * (-10719068.0 / 638512875.0)));
+    r = fma(r, u, sreg(5.0 * (-10196.0 / 467775.0)));
+    r = fma(r, u, sreg(4.0 * (-428.0 / 14175.0)));
+    r = fma(r, u, sreg(3.0 * (-44.0 / 945.0)));
+    r = fma(r, u, sreg(2.0 * (-4.0 / 45.0)));
+    return fma(r, u, sreg(-1.0 / 3.0));
 }
 
 // Cotangents of one node's quantities (rho, U, beta, log rho, log beta, |U|^2).
@@ -569,11 +569,11 @@ __device__ __forceinline__ void face_term_vjp(const VjpArgs &a, const Node &me, 
         }
     }
     if (a.iface_diss == 1) {  // Lax-Friedrichs; the matrix dissipation has a pass of its own
-        const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double nn = sqrt_pos(n0 * n0 + n1 * n1 + n2 * n2);
         const double unm = me.u1 * n0 + me.u2 * n1 + me.u3 * n2;
-        const double cme = sqrt(a.gamma * Pme / me.rho);
+        const double cme = sqrt_pos(a.gamma * Pme * rcp(me.rho));
         const double li = fabs(unm) + cme * nn;
-        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt(a.gamma * Pn / o.rho) * nn;
+        const double lo = fabs(o.u1 * n0 + o.u2 * n1 + o.u3 * n2) + sqrt_pos(a.gamma * Pn * rcp(o.rho)) * nn;
         const double lam = fmax(li, lo);
         double t_own = 0.0, t_nb = 0.0;
 #pragma unroll
@@ -1067,11 +1067,11 @@ __device__ __forceinline__ void matrix_dissipation_vjp(const Node &a, const Node
     const double ibeta_hat = ser_b ? 2.0 * isb * Fb : (a.lbeta - b.lbeta) * idb;
     const double p_hat = 0.5 * sr * isb;
     const double irh = rcp(rho_hat);
-    const double a_hat = sqrt(gamma * p_hat * irh);
+    const double a_hat = sqrt_pos(gamma * p_hat * irh);
     const double u[3] = {0.5 * (a.u1 + b.u1), 0.5 * (a.u2 + b.u2), 0.5 * (a.u3 + b.u3)};
     const double ubsq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const double h_hat = 0.5 * gamma / gm1 * ibeta_hat + ubsq - 0.25 * (a.k + b.k);
-    const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    const double nn = sqrt_pos(n0 * n0 + n1 * n1 + n2 * n2);
     const double inn = rcp(nn);
     const double en[3] = {n0 * inn, n1 * inn, n2 * inn};
     const double vn = u[0] * en[0] + u[1] * en[1] + u[2] * en[2];
