@@ -29,49 +29,51 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 FP64 FMA lanes/clk x 2 flop x 2.4 G
 
 
 # ------------------------------------------------------------------------------------------
-# Algorithmic work of the main residual kernel (per launch), from the per-unit figures derived
-# for the method: a pair is one unordered node pair on a line (3 N^2 lines x N(N-1)/2 pairs per
-# element), a face side is one (node, face) incidence (6 N^2 per element).
+# Algorithmic work of the main residual kernel (per launch).
+# Bytes: the compulsory 160 B per node (q 40 + metric 72 + J 8 read, dq/dt 40 written).  The face
+# traces of the contravariant viscous flux that the kernel writes for its neighbours' SAT^V are an
+# implementation choice and are reported separately, not counted as algorithmic.
+# FP64: the oracle's own operations, counted by oracle/opcount.py (each +, -, *, /, sqrt, log is one
+# operation; the branch not taken and structural zeros are not counted): per unordered volume pair
+# (3 N^2 lines x N(N-1)/2 pairs per element) and for the rest of the residual per element.
+# tests/test_oracle_opcount.py checks this table against the counter.
 # ------------------------------------------------------------------------------------------
-FLOP_PAIR = 70          # two-point flux contracted with A_i + A_j, applied to both nodes
-FLOP_FACE_INV = 95      # EC interface flux + Lax-Friedrichs dissipation, one side
-FLOP_NODE_INV = 30      # primitives, logarithms, final 1/J scaling
-FLOP_FACE_VISC = 330    # SAT^theta, own SAT^V, interior penalty (two viscous-flux evaluations)
-BYTES_NODE = 160        # q 40 + metric 72 + J 8 read, dq/dt 40 written
-
-
-def flop_visc_node(N):
-    # theta (3 directions x 4 comps x N FMA), g (12 x 3 FMA + scale), viscous flux and three
-    # contractions (~145), divergence (3 x 4 x N FMA)
-    return 24 * N + 75 + 145 + 24 * N
+BYTES_NODE = 160
+ORACLE_OPS = {  # (p, viscous): (operations per volume pair, operations of the rest per element)
+    (3, False): (183, 29504),
+    (4, True): (183, 249591),
+    (4, False): (183, 46225),
+    (7, True): (183, 828840),
+}
 
 
 def algorithmic_flops(p, K, viscous):
+    """Oracle-counted FP64 operations of one residual, or None if the table has no entry."""
+    ops = ORACLE_OPS.get((p, viscous))
+    if ops is None:
+        return None
     N = p + 1
-    pairs = K * 3 * N * N * N * (N - 1) // 2
-    faces = K * 6 * N * N
-    nodes = K * N ** 3
-    f = pairs * FLOP_PAIR + faces * FLOP_FACE_INV + nodes * FLOP_NODE_INV
-    if viscous:
-        f += nodes * flop_visc_node(N) + faces * FLOP_FACE_VISC
-    return f
+    return K * (3 * N * N * N * (N - 1) // 2 * ops[0] + ops[1])
 
 
-def algorithmic_bytes(p, K, viscous):
+def algorithmic_bytes(p, K):
+    return K * (p + 1) ** 3 * BYTES_NODE
+
+
+def trace_bytes(p, K, viscous):
+    """Face traces of the contravariant viscous flux written per launch (implementation-added)."""
     N = p + 1
-    b = K * N ** 3 * BYTES_NODE
-    if viscous:
-        b += K * 6 * N * N * 4 * 8   # face traces of the contravariant viscous flux (written)
-    return b
+    return K * 6 * N * N * 4 * 8 if viscous else 0
 
 
-# HBM traffic of the main residual kernel measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on
-# this workload (KiB per dispatch, scaled by the same counters' reading for a plain 512 MiB device
-# copy: FETCH x2.0, WRITE x1.0).  Valid only for the kernel source it was measured on.
-TRAFFIC = {"sha256": "f32098077683836208571f657512c15743e029da53ad064848b5b7bf82fcbf40",
-           "workload": "ns_tgv_p4_e32",
-           # bytes per launch by residual schedule index (degree 4)
-           "bytes": {0: 1313471008, 1: 1296047112, 2: 1036740304, 3: 1025980944, 4: 1313494904, 5: 1295059104, 6: 1274174944}}
+# rocprofv3 measurements of the main residual kernel on one workload, valid only for the kernel
+# source they were taken on (sha256 of KERNEL_SOURCES); copied from profiles/ (the summary there
+# gives the commands).  Per residual schedule index:
+#   bytes:    HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch x 1024; the
+#             factors are those counters' readings for a plain 512 MiB device copy);
+#   trace_ms: average duration from --kernel-trace --stats;
+#   hw_flops: hardware FP64 operations per launch, (ADD + MUL + 2 FMA + TRANS) F64 x 64 lanes.
+KERNEL_PROFILE = {"sha256": None, "workload": "ns_tgv_p4_e32", "bytes": {}, "trace_ms": {}, "hw_flops": {}}
 KERNEL_SOURCES = ("paper_1911_10966_amd/csrc/sbp_kernels.hip", "paper_1911_10966_amd/csrc/sbp_device.h")
 
 
@@ -84,15 +86,51 @@ def kernel_sha():
     return h.hexdigest()
 
 
-def traffic_for_current_kernel(workload, schedule):
-    if TRAFFIC["sha256"] != kernel_sha() or workload != TRAFFIC["workload"]:
+def _profiled(workload, key, schedule):
+    if KERNEL_PROFILE["sha256"] != kernel_sha() or workload != KERNEL_PROFILE["workload"]:
         return None
-    return TRAFFIC["bytes"].get(schedule)
+    return KERNEL_PROFILE[key].get(schedule)
+
+
+def traffic_for_current_kernel(workload, schedule):
+    return _profiled(workload, "bytes", schedule)
+
+
+def trace_ms_for_current_kernel(workload, schedule):
+    return _profiled(workload, "trace_ms", schedule)
+
+
+def hw_flops_for_current_kernel(workload, schedule):
+    return _profiled(workload, "hw_flops", schedule)
 
 
 # ------------------------------------------------------------------------------------------
-def cpu_leg(workload: str, n_sample: int, seed: int = 11):
-    """Oracle timing on a bounded element sample (run in a child with one thread)."""
+_CPU = {}
+
+
+def _oracle_chunk(elems):
+    from oracle import residual as R
+    c = _CPU
+    R.residual(c["q"], c["metric"], c["jac"], c["nbr"], c["sbp"], c["prm"], elems=elems, chunk=1024)
+    return len(elems)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(workload: str, n_sample: int, workers: int):
+    """The plain NumPy oracle on the first `n_sample` elements of the workload (all by default), as
+    `workers` contiguous blocks evaluated by forked processes of one thread each; one block is
+    first evaluated alone on one process (the single-core figure)."""
+    import multiprocessing
     import numpy as np
     import torch
 
@@ -104,35 +142,51 @@ def cpu_leg(workload: str, n_sample: int, seed: int = 11):
     x = W.coords(prob, sbp.x).numpy()
     q = W.state(prob, torch.as_tensor(x)).numpy()
     nbr = W.neighbours(prob.E)
-    rng = np.random.Generator(np.random.PCG64(seed))
-    S = np.sort(rng.choice(prob.K, size=n_sample, replace=False))
+    n_sample = min(n_sample, prob.K)
+    S = np.arange(n_sample)
     ring = np.unique(np.concatenate([S, nbr[S].ravel(), nbr[nbr[S].ravel()].ravel()]))
     metric = np.zeros((9,) + x.shape[1:])
     jac = np.ones(x.shape[1:])
     metric[:, ring] = geometry.curl_metrics(x[:, ring], sbp.D)
     jac[ring] = geometry.jacobian(x[:, ring], sbp.D)
-    prm = R.Params.of(prob)
+    _CPU.update(q=q, metric=metric, jac=jac, nbr=nbr, sbp=sbp, prm=R.Params.of(prob))
+    N3 = prob.N ** 3
+    blocks = [b for b in np.array_split(S, workers) if len(b)]
     t0 = time.perf_counter()
-    R.residual(q, metric, jac, nbr, sbp, prm, elems=S, chunk=1024)
-    t = time.perf_counter() - t0
-    nodes = n_sample * prob.N ** 3
-    print(json.dumps({"value": nodes / t / 1e6, "seconds": t, "nodes": nodes, "elems": int(n_sample)}))
+    _oracle_chunk(blocks[0])
+    t1 = time.perf_counter() - t0
+    with multiprocessing.get_context("fork").Pool(len(blocks)) as pool:
+        pool.map(_oracle_chunk, [b[:1] for b in blocks])   # workers started and warm
+        t0 = time.perf_counter()
+        pool.map(_oracle_chunk, blocks, chunksize=1)
+        tw = time.perf_counter() - t0
+    print(json.dumps({"value": n_sample * N3 / tw / 1e6, "seconds": tw, "elems": int(n_sample),
+                      "nodes": int(n_sample * N3), "workers": len(blocks),
+                      "single_value": len(blocks[0]) * N3 / t1 / 1e6, "single_seconds": t1,
+                      "single_elems": int(len(blocks[0]))}))
 
 
 def run_cpu_baseline(workload: str, n_sample: int):
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count() or 1
+    workers = max(1, min(16, avail))
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[k] = "1"
     env["CUDA_VISIBLE_DEVICES"] = ""
     env["HIP_VISIBLE_DEVICES"] = ""
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", workload,
-           "--cpu-sample", str(n_sample)]
+           "--cpu-sample", str(n_sample), "--cpu-workers", str(workers)]
     res = subprocess.run(cmd, capture_output=True, text=True, env=env, cwd=ROOT)
     if res.returncode != 0:
         sys.stderr.write(res.stderr)
         return None
-    return json.loads(res.stdout.strip().splitlines()[-1])
-
+    out = json.loads(res.stdout.strip().splitlines()[-1])
+    out["nproc"] = os.cpu_count()
+    out["cpu_model"] = cpu_model()
+    return out
 
 
 # ------------------------------------------------------------------------------------------
@@ -496,7 +550,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ns_tgv_p4_e32")
-    ap.add_argument("--cpu-sample", type=int, default=32768, help="elements in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=32768,
+                    help="elements in the oracle sample run on all host cores (at most 16)")
+    ap.add_argument("--cpu-workers", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--kernel-reps", type=int, default=0,
@@ -524,7 +580,7 @@ def main():
     args = ap.parse_args()
 
     if args.cpu_leg:
-        cpu_leg(args.workload, args.cpu_sample)
+        cpu_leg(args.workload, args.cpu_sample, args.cpu_workers)
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
@@ -573,28 +629,29 @@ def main():
     schedule = ps.autotune(q, reps=3)[0]
     out = torch.empty_like(q)
 
-    live_ms = []  # duration of the main residual kernel in every timed step (HIP events)
-
-    def step(record=None):
-        if record is None:
-            ps.residual(q, out)
+    def step(record):
+        if record:
+            # events around the main residual kernel on its launch stream, read after the loop
+            ps.profile_residual(q, out, wait=False)
         else:
-            record.append(ps.profile_residual(q, out))
+            ps.residual(q, out)
         ps.rk_step(q, dt, 1)
 
     for _ in range(args.warmup):
-        step()
+        step(False)
     ps.status()
+    P.profile_collect()
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        step(live_ms)
+        step(True)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
+    n_live, live_total = P.profile_collect()
     ps.status()
     ms_step = ms_total / args.steps
     res_per_step = 5
@@ -603,14 +660,16 @@ def main():
 
     # dominant kernel: the fused residual kernel, timed with events on its launch stream in every
     # timed step (plus optional extra launches after the timed region)
-    kms = live_ms + [ps.profile_residual(q, out) for _ in range(args.kernel_reps)]
-    kmean = sum(kms) / len(kms)
+    for _ in range(args.kernel_reps):
+        ps.profile_residual(q, out, wait=False)
+    n_extra, extra_total = P.profile_collect()
+    kmean = (live_total + extra_total) / (n_live + n_extra)
     visc = prob.mu > 0
     flops = algorithmic_flops(prob.p, prob.K, visc)
-    nbytes = algorithmic_bytes(prob.p, prob.K, visc)
-    alu = flops / (kmean * 1e-3) / 1e12
+    nbytes = algorithmic_bytes(prob.p, prob.K)
     hbm = nbytes / (kmean * 1e-3) / 1e9
-    if alu / FP64_VALU_PEAK_TFLOPS >= hbm / HBM_PEAK_GBS:
+    alu = flops / (kmean * 1e-3) / 1e12 if flops is not None else None
+    if alu is not None and alu / FP64_VALU_PEAK_TFLOPS >= hbm / HBM_PEAK_GBS:
         roof = {"bound": "alu", "achieved": round(alu, 3), "peak": FP64_VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(alu / FP64_VALU_PEAK_TFLOPS, 4)}
     else:
@@ -620,8 +679,16 @@ def main():
     roof["schedule"] = schedule
     roof["kernel"] = "k_residual"
     roof["kernel_ms"] = round(kmean, 4)
+    roof["kernel_launches_timed"] = n_live + n_extra
+    roof["kernel_ms_trace"] = trace_ms_for_current_kernel(args.workload, schedule)
+    roof["bytes_algorithmic"] = nbytes
+    roof["bytes_implementation_added"] = trace_bytes(prob.p, prob.K, visc)
     roof["hbm_GBps_algorithmic"] = round(hbm, 1)
-    roof["fp64_TFLOPs_algorithmic"] = round(alu, 3)
+    roof["hbm_frac"] = round(hbm / HBM_PEAK_GBS, 4)
+    roof["fp64_ops_oracle_count"] = flops
+    roof["fp64_TFLOPs_algorithmic"] = round(alu, 3) if alu is not None else None
+    roof["fp64_frac"] = round(alu / FP64_VALU_PEAK_TFLOPS, 4) if alu is not None else None
+    roof["fp64_hw_flops"] = hw_flops_for_current_kernel(args.workload, schedule)
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -650,9 +717,13 @@ def main():
         if r is not None:
             which = (f"all {r['elems']} elements" if r["elems"] >= prob.K
                      else f"{r['elems']} randomly chosen elements")
-            cpu = {"value": round(r["value"], 4), "unit": UNIT, "cores": 1, "kind": "oracle",
-                   "sample": f"one residual of {which} "
-                             f"({r['nodes']} nodes) of {args.workload}, {r['seconds']:.1f} s"}
+            cpu = {"value": round(r["value"], 4), "unit": UNIT, "cores": r["workers"], "kind": "oracle",
+                   "sample": f"one residual of {which} ({r['nodes']} nodes) of {args.workload} split "
+                             f"into {r['workers']} contiguous blocks on as many processes of one "
+                             f"thread, {r['seconds']:.1f} s; one block ({r['single_elems']} elements) "
+                             f"alone on one process: {r['single_seconds']:.1f} s",
+                   "single_core_value": round(r["single_value"], 4),
+                   "nproc": r["nproc"], "cpu_model": r["cpu_model"]}
 
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,

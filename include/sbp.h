@@ -177,10 +177,18 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
 
 /* Profiling variant of sbp_residual for one problem (n_prob == 1): the same launches, with HIP
  * events recorded on `stream` around the main residual kernel (around all plane passes for
- * p > 8); waits for the end event and stores
- * that kernel's duration in *kernel_ms (host pointer).  Not for use under graph capture. */
+ * p > 8).  With kernel_ms (host pointer) the call waits for the end event and stores that kernel's
+ * duration in *kernel_ms.  With kernel_ms NULL it only records the events, into the next of at
+ * most SBP_PROFILE_SLOTS slots (SBP_ERR_ARG when all are taken), and returns without waiting;
+ * sbp_profile_collect() reads them.  Not thread-safe; not for use under graph capture. */
+#define SBP_PROFILE_SLOTS 4096
 int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
                          void *ws, size_t ws_bytes, void *stream, float *kernel_ms);
+
+/* Waits for every launch recorded by sbp_profile_residual with kernel_ms NULL since the last call,
+ * stores their number in *count and the sum of their main-kernel durations (ms) in *total_ms (host
+ * pointers), and empties the slots. */
+int sbp_profile_collect(int32_t *count, double *total_ms);
 
 /* Autotuner: for each group of problems sharing degree, viscosity on/off and flux, times every
  * schedule of the residual kernel (elements per workgroup, one block per element tile or a

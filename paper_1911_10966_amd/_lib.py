@@ -16,6 +16,7 @@ SBP_ERR_WORKSPACE = -6
 SBP_ERR_SCRATCH = -7
 SBP_NOALLOC_SCRATCH_BYTES = 64 << 20
 SBP_NOALLOC_MAX_PROBLEMS = 16
+SBP_PROFILE_SLOTS = 4096
 SBP_MAX_P = 15
 SBP_MAX_VJP_P = 8
 SBP_BC_DIRICHLET = -1
@@ -25,7 +26,7 @@ SBP_BC_ADIABATIC_WALL = -3
 EXPORTED = ("sbp_version", "sbp_error_string", "sbp_lgl_operator", "sbp_metrics",
             "sbp_workspace_bytes", "sbp_residual", "sbp_rk_step", "sbp_residual_vjp",
             "sbp_profile_residual", "sbp_autotune", "sbp_schedule_count", "sbp_set_schedule",
-            "sbp_status", "sbp_release", "sbp_residual_noalloc")
+            "sbp_status", "sbp_release", "sbp_residual_noalloc", "sbp_profile_collect")
 
 
 class sbp_problem(ctypes.Structure):
@@ -85,6 +86,7 @@ def lib():
         L.sbp_set_schedule.argtypes = [P, i32, vp, sz, i32, i32]
         L.sbp_autotune.argtypes = [P, i32, vp, vp, vp, sz, vp, i32, ctypes.POINTER(i32)]
         L.sbp_profile_residual.argtypes = [P, i32, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_float)]
+        L.sbp_profile_collect.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 

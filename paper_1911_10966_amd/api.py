@@ -191,15 +191,16 @@ class ProblemSet:
               "sbp_residual_noalloc")
         return out, status
 
-    def profile_residual(self, q: torch.Tensor, out: torch.Tensor) -> float:
-        """Runs the residual once and returns the main kernel's duration in ms (HIP events)."""
+    def profile_residual(self, q: torch.Tensor, out: torch.Tensor, wait: bool = True):
+        """Runs the residual once with HIP events around the main kernel.  wait=True returns its
+        duration in ms; wait=False only records the events (read later by profile_collect())."""
         self._check_state(q, "q")
         self._check_state(out, "out")
         ms = ctypes.c_float(0.0)
         check(lib().sbp_profile_residual(self._arr, self.n, _ptr(q), _ptr(out), _ptr(self.ws),
-                                         self.ws_bytes, _stream(), ctypes.byref(ms)),
+                                         self.ws_bytes, _stream(), ctypes.byref(ms) if wait else None),
               "sbp_profile_residual")
-        return float(ms.value)
+        return float(ms.value) if wait else None
 
     def autotune(self, q: torch.Tensor, reps: int = 3):
         """Times every residual schedule on these inputs and keeps the fastest per group; returns
@@ -243,6 +244,15 @@ class ProblemSet:
         rc = lib().sbp_status(_ptr(self.ws), _stream(), ctypes.byref(flags))
         check(rc, "sbp_status")
         return flags.value
+
+
+def profile_collect():
+    """(count, total ms) of the main-kernel launches recorded with profile_residual(wait=False)
+    since the last call; waits for them."""
+    n = ctypes.c_int32(0)
+    tot = ctypes.c_double(0.0)
+    check(lib().sbp_profile_collect(ctypes.byref(n), ctypes.byref(tot)), "sbp_profile_collect")
+    return int(n.value), float(tot.value)
 
 
 class SBPResidual(torch.autograd.Function):

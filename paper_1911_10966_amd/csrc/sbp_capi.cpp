@@ -629,17 +629,46 @@ int sbp_residual_vjp(const sbp_problem *probs, int32_t n_prob, const double *q, 
     return SBP_OK;
 }
 
+namespace {
+// Event pairs of the launches recorded without waiting (sbp_profile_residual with kernel_ms NULL).
+struct ProfileRing {
+    std::vector<hipEvent_t> begin, end;
+    int recorded = 0;
+};
+ProfileRing g_ring;
+std::mutex g_ring_mu;
+}  // namespace
+
 int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double *q, double *dqdt,
                          void *ws, size_t ws_bytes, void *stream, float *kernel_ms) {
     Layout L;
     int rc = validate(probs, n_prob, ws, ws_bytes, L);
     if (rc != SBP_OK) return rc;
-    if (n_prob != 1 || kernel_ms == nullptr || !aligned8(q) || !aligned8(dqdt) || q == dqdt)
-        return SBP_ERR_ARG;
+    if (n_prob != 1 || !aligned8(q) || !aligned8(dqdt) || q == dqdt) return SBP_ERR_ARG;
     sbp::KernelTimer &tm = sbp::residual_timer();
-    if (tm.begin == nullptr) {
-        if (hipEventCreate(&tm.begin) != hipSuccess || hipEventCreate(&tm.end) != hipSuccess)
-            return SBP_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_ring_mu);
+    if (kernel_ms == nullptr) {
+        // record into the next slot of the ring, do not wait
+        if (g_ring.recorded >= SBP_PROFILE_SLOTS) return SBP_ERR_ARG;
+        if (g_ring.recorded == (int)g_ring.begin.size()) {
+            hipEvent_t b = nullptr, e = nullptr;
+            if (hipEventCreate(&b) != hipSuccess) return SBP_ERR_HIP;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipEventDestroy(b);
+                return SBP_ERR_HIP;
+            }
+            g_ring.begin.push_back(b);
+            g_ring.end.push_back(e);
+        }
+        tm.begin = g_ring.begin[g_ring.recorded];
+        tm.end = g_ring.end[g_ring.recorded];
+    } else {
+        static hipEvent_t b0 = nullptr, e0 = nullptr;
+        if (b0 == nullptr) {
+            if (hipEventCreate(&b0) != hipSuccess || hipEventCreate(&e0) != hipSuccess) return SBP_ERR_HIP;
+        }
+        tm.begin = b0;
+        tm.end = e0;
     }
     Plan *plan = get_plan(probs, n_prob, static_cast<char *>(ws), L);
     if (!plan) return SBP_ERR_HIP;
@@ -648,8 +677,29 @@ int sbp_profile_residual(const sbp_problem *probs, int32_t n_prob, const double 
                         plan->groups[0].variant);
     tm.enabled = false;
     if (rc != SBP_OK) return rc;
+    if (kernel_ms == nullptr) {
+        ++g_ring.recorded;
+        return SBP_OK;
+    }
     if (hipEventSynchronize(tm.end) != hipSuccess) return SBP_ERR_HIP;
     if (hipEventElapsedTime(kernel_ms, tm.begin, tm.end) != hipSuccess) return SBP_ERR_HIP;
+    return SBP_OK;
+}
+
+int sbp_profile_collect(int32_t *count, double *total_ms) {
+    if (count == nullptr || total_ms == nullptr) return SBP_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_ring_mu);
+    double sum = 0.0;
+    for (int i = 0; i < g_ring.recorded; ++i) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(g_ring.end[i]) != hipSuccess ||
+            hipEventElapsedTime(&ms, g_ring.begin[i], g_ring.end[i]) != hipSuccess)
+            return SBP_ERR_HIP;
+        sum += ms;
+    }
+    *count = g_ring.recorded;
+    *total_ms = sum;
+    g_ring.recorded = 0;
     return SBP_OK;
 }
 

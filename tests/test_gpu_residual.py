@@ -129,3 +129,21 @@ def test_metrics_match_oracle():
         j = j.cpu().numpy().reshape(c.jac.shape)
         assert np.abs(m - c.metric).max() < 1e-13 * np.abs(c.metric).max() * p
         assert np.abs(j - c.jac).max() < 1e-13 * np.abs(c.jac).max() * p
+
+
+def test_profiled_launches_recorded_without_waiting():
+    """profile_residual(wait=False) records events only; profile_collect returns their number and
+    total duration, and the result equals the plain residual."""
+    require_gpu()
+    c = Case(W.make_problem(p=4, E=3, L=2.0, A=0.1, mu=0.01, seed=8, u_rms=0.3))
+    ps = P.ProblemSet([device_problem(c)])
+    qd = to_dev(c.q)
+    out = torch.empty_like(qd)
+    P.profile_collect()
+    for _ in range(3):
+        assert ps.profile_residual(qd, out, wait=False) is None
+    n, total = P.profile_collect()
+    assert n == 3 and total > 0.0
+    assert P.profile_collect() == (0, 0.0)
+    assert ps.profile_residual(qd, out) > 0.0
+    assert torch.equal(out, ps.residual(qd))
