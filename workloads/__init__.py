@@ -9,6 +9,6 @@ viscous error-vs-cost study with its forcing (``workloads.mms``).
 from .inputs import (  # noqa: F401
     Problem, make_problem, config, CONFIG_NAMES, batch_config,
     coords, state, neighbours, cotangent, direction, cfl_dt, mms_problem,
-    channel_problem, problem_neighbours, jumped_state,
+    channel_problem, problem_neighbours, jumped_state, mapping_jacobian,
 )
 from . import mms  # noqa: F401

@@ -195,6 +195,30 @@ def coords(prob: Problem, xi1d, device="cpu") -> torch.Tensor:
     return x.reshape(3, E ** 3, N, N, N).contiguous()
 
 
+def mapping_jacobian(prob: Problem, xi1d) -> np.ndarray:
+    """dx_m/dxi_i of the mapping of coords() at the nodes, evaluated from its closed form, shape
+    (3, 3, K, N, N, N) (entry [m][i]).  With g_d = (L/E)(e_d + (xi_d + 1)/2) and
+    x_d = g_d + b(g), b = A (L/2) sin(w g_1) sin(w g_2) sin(w g_3), w = 2 pi/L:
+    dx_m/dxi_i = (L/(2E)) (delta_mi + A (L/2) w cos(w g_i) prod_{j != i} sin(w g_j))."""
+    E, N, L = prob.E, prob.N, prob.L
+    xi = np.asarray(xi1d, dtype=np.float64)
+    assert xi.size == N
+    h = L / E
+    g1d = h * (np.arange(E, dtype=np.float64)[:, None] + (xi[None, :] + 1.0) * 0.5)
+    g = [np.broadcast_to(g1d[None, None, :, None, None, :], (E, E, E, N, N, N)),
+         np.broadcast_to(g1d[None, :, None, None, :, None], (E, E, E, N, N, N)),
+         np.broadcast_to(g1d[:, None, None, :, None, None], (E, E, E, N, N, N))]
+    w = 2.0 * math.pi / L
+    sn = [np.sin(w * gi) for gi in g]
+    cs = [np.cos(w * gi) for gi in g]
+    out = np.zeros((3, 3, E, E, E, N, N, N))
+    for i in range(3):
+        db = prob.A * (L / 2.0) * w * cs[i] * sn[(i + 1) % 3] * sn[(i + 2) % 3]
+        for m in range(3):
+            out[m, i] = 0.5 * h * ((1.0 if m == i else 0.0) + db)
+    return out.reshape(3, 3, E ** 3, N, N, N)
+
+
 # ----------------------------------------------------------------------------------
 # Fields
 # ----------------------------------------------------------------------------------
