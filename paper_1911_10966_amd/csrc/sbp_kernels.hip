@@ -27,7 +27,7 @@ constexpr int kFaceItemsFrom = 6;
 // a face-orientation table (unstructured faces); without it the aligned partners are compiled in.
 template <int N, int EPW, bool VISC, int FLUX, bool MD, bool OR>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
-                                              const double *s_D) {
+                                              const double *s_D, int *s_face) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
     constexpr bool COMPACT = !VISC;  // see tile_fields
     constexpr int LDS_FIELDS = tile_fields(VISC);
@@ -82,6 +82,20 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         s_buf[F_LR * NODES + tid] = me.lrho;
         s_buf[F_LB * NODES + tid] = me.lbeta;
         if constexpr (!COMPACT) s_buf[F_K * NODES + tid] = me.k;
+    }
+    // neighbour index and kind of the tile's faces, decoded once per face (visible to all threads
+    // after the first barrier below); a mesh error is flagged here
+    if (tid < EPW * 6) {
+        const long long ee = ebase + tid / 6;
+        int nbv = 0, kind = FACE_INVALID;
+        if (ee < a.K) {
+            const long long nb = a.nbr[ee * 6 + tid % 6];
+            kind = face_kind(a, nb);
+            if (kind == FACE_INVALID) atomicOr(a.status, FLAG_MESH);
+            nbv = (int)nb;
+        }
+        s_face[2 * tid] = nbv;
+        s_face[2 * tid + 1] = kind;
     }
 
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -215,10 +229,9 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             double v[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) v[c] = 0.0;
-            const long long nb = ee < a.K ? (long long)a.nbr[ee * 6 + f] : 0;
-            const int kind = ee < a.K ? face_kind(a, nb) : 0;
-            if (ee < a.K && kind == 0) atomicOr(a.status, FLAG_MESH);
-            if (kind != 0) {
+            const long long nb = s_face[2 * (es * 6 + f)];
+            const int kind = s_face[2 * (es * 6 + f) + 1];
+            if (kind != FACE_INVALID) {
                 const int il = side ? N - 1 : 0;
                 const int ta = t % N, tb = t / N;
                 const int lno = l == 0 ? il + N * ta + N2 * tb
@@ -270,7 +283,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int il = idx[l];
                 if (il != 0 && il != N - 1) continue;
                 const int side = (il == N - 1) ? 1 : 0;
-                const int kind = face_kind(a, a.nbr[e * 6 + 2 * l + side]);
+                const int kind = s_face[2 * (slot * 6 + 2 * l + side) + 1];
                 if (kind == FACE_INVALID) continue;
                 if (kind == FACE_INTERIOR) faces |= 1 << l;
                 if (kind == FACE_WALL) wfaces |= 1 << l;
@@ -289,12 +302,9 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 const int il = idx[l];
                 if (il != 0 && il != N - 1) continue;
                 const int side = (il == N - 1) ? 1 : 0;
-                const long long nb = a.nbr[e * 6 + 2 * l + side];
-                const int kind = face_kind(a, nb);
-                if (kind == 0) {
-                    atomicOr(a.status, FLAG_MESH);
-                    continue;
-                }
+                const long long nb = s_face[2 * (slot * 6 + 2 * l + side)];
+                const int kind = s_face[2 * (slot * 6 + 2 * l + side) + 1];
+                if (kind == FACE_INVALID) continue;
                 if (kind == FACE_INTERIOR) faces |= 1 << l;
                 if (kind == FACE_WALL) wfaces |= 1 << l;
                 sfaces |= 1 << l;
@@ -441,18 +451,19 @@ k_residual(const GroupArgs g) {
     constexpr int N2 = N * N, NODES = EPW * N * N * N;
     __shared__ double s_buf[tile_fields(VISC) * NODES];
     __shared__ double s_D[N2];
+    __shared__ int s_face[2 * 6 * EPW];
     if (threadIdx.x < N2) s_D[threadIdx.x] = g.D[threadIdx.x];
     if constexpr (!PERSIST) {
         const long long vb = xcd_block(blockIdx.x, gridDim.x);
         const int b = find_problem(g.block_start, g.n, vb);
         const ResArgs a = problem_view(g, g.probs[b], g.out);
-        residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+        residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D, s_face);
     } else {
         for (long long it = blockIdx.x; it < g.total_blocks; it += gridDim.x) {
             const long long vb = xcd_block(it, g.total_blocks);
             const int b = find_problem(g.block_start, g.n, vb);
             const ResArgs a = problem_view(g, g.probs[b], g.out);
-            residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D);
+            residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D, s_face);
             __syncthreads();
         }
     }
