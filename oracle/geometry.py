@@ -187,11 +187,17 @@ def surface_metrics(metric, sbp, nbr):
     K = metric.shape[1]
     G, cols, held = surface_system(sbp, nbr)
     # minimum-norm solution x = G^T y, (G G^T) y = rhs, with the eigenvalues of G G^T below 1e-12 of
-    # the largest dropped (directions the constraints cannot move; rounding noise of rhs along
-    # them would otherwise be amplified).  Dense: meant for the mesh sizes of the tests.
+    # the squared norm of one element's conditions dropped (directions the constraints cannot move;
+    # rounding noise of rhs along them would otherwise be amplified).  The scale is that of the
+    # conditions themselves, not the largest eigenvalue of the mesh's G G^T: on a mesh where every
+    # condition vanishes identically (one element, periodic: its opposite faces are one face) all
+    # eigenvalues are rounding noise and none may be kept.  Dense: meant for the mesh sizes of the
+    # tests.
+    M, held_e, _, Y = gcl_operator(sbp.D)
+    c_scale = np.linalg.norm(Y.T @ M[:, held_e], 2) ** 2
     gram = (G @ G.T).toarray()
     lam, V = np.linalg.eigh(gram)
-    keep = lam > 1e-12 * lam[-1]
+    keep = lam > 1e-12 * c_scale
     count = np.zeros(G.shape[1])
     np.add.at(count, cols.ravel(), 1.0)
     out = metric.copy()

@@ -148,3 +148,17 @@ def test_entropy_conservation_and_conservation():
     tot = (wJ[None] * r).reshape(5, -1).sum(1)
     mag = (wJ[None] * np.abs(r)).reshape(5, -1).sum(1)
     assert np.all(np.abs(tot) < 1e-13 * mag)
+
+
+def test_one_element_periodic_mesh_needs_no_surface_correction():
+    """With one element, periodic, each pair of opposite faces is one face: x_+ - x_- vanishes in
+    every compatibility condition, so no condition constrains the surface values.  The correction
+    must then be exactly zero (the face values stay the means of the analytic ones), and the result
+    still satisfies the discrete GCL."""
+    prob, sbp, F = _mesh(4, 1, A=0.1)
+    nbr = W.neighbours(1)
+    a0, _ = Gm.analytic_metrics(F)
+    surf, xs = Gm.surface_metrics(a0, sbp, nbr)
+    assert np.array_equal(xs, np.zeros_like(xs))
+    m, _ = Gm.optimized_metrics(F, nbr, sbp)
+    assert np.abs(Gm.gcl_residual(m, sbp.D)).max() < 1e-13 * np.abs(m).max()
