@@ -383,19 +383,23 @@ def cost_experiment(P, W, dev, steps):
     return out
 
 
-def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=2000):
+def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=1000):
     """The paper's robustness study of the Taylor-Green vortex (Re = 1600, Ma = 0.05, Cartesian
     periodic box of side 2 pi, t_f = 20): for each mesh of E^3 elements and degree p, the ES-C,
     SF-KG and DC discretizations are advanced together as one batched problem set (three graph
-    branches) with classical RK4 at dt = cfl (L/E) / ((p+1)^2 max(|U| + c)).  A run has failed when
-    its state holds a non-finite value or a non-positive density or pressure; failed runs leave the
-    set.  Reports, per run, success or the time of failure and, for runs that reach t_f, the
-    kinetic energy relative to its initial value."""
+    branches) with classical RK4 under CFL control: every `chunk` steps the time step is set again
+    to dt = cfl (L/E) / ((p+1)^2 max(|U| + c)) from the current states (the smallest over the
+    schemes still running, so that they stay at one time), and the last steps are shortened to end
+    at t_f.  A run has failed when its state holds a non-finite value or a non-positive density or
+    pressure; failed runs leave the set.  Reports, per run, success or the time of failure and, for
+    runs that reach t_f, the kinetic energy relative to its initial value."""
     import math
     import torch
     Ma = 0.05
+    gam = 1.4
     schemes = (("ES-C", 0), ("SF-KG", 2), ("DC", 3))
-    out = {"t_final": t_final, "cfl": cfl, "Ma": Ma, "Re": 1600, "integrator": "classical RK4, fixed dt",
+    out = {"t_final": t_final, "cfl": cfl, "Ma": Ma, "Re": 1600,
+           "integrator": f"classical RK4, dt from the current max(|U|+c) every {chunk} steps",
            "results": []}
     t_start = time.time()
     for E in meshes:
@@ -405,68 +409,83 @@ def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=200
                     out["results"].append({"E": E, "p": p, "scheme": name, "result": "not run (time budget)"})
                 continue
             probs = [W.make_problem(name=f"tgv_robust_p{p}_e{E}", p=p, E=E, L=2.0 * math.pi, A=0.0,
-                                    gamma=1.4, R=1.0 / (1.4 * Ma * Ma), mu=1.0 / 1600.0, Pr=0.72,
+                                    gamma=gam, R=1.0 / (gam * Ma * Ma), mu=1.0 / 1600.0, Pr=0.72,
                                     init="tgv", Ma=Ma, two_point=tp) for _, tp in schemes]
             built = [device_problem(P, W, pr, dev) for pr in probs]
-            dt0 = built[0][2] * (cfl / 0.25)   # device_problem uses cfl 0.25
-            n_total = int(math.ceil(t_final / dt0))
-            dt = t_final / n_total
+            h = probs[0].L / E
             _, w, _ = P.lgl_operator(p)
             wt = torch.as_tensor(w, dtype=torch.float64, device=dev)
             w3 = (wt[None, None, :, None, None] * wt[None, None, None, :, None] * wt[None, None, None, None, :])
             wJ = (w3.reshape(1, 1, -1) * built[0][0].jac.reshape(probs[0].K, -1)[None]).reshape(-1)
 
-            def kinetic(qq):
+            def prim(qq):
                 q5 = qq.reshape(5, -1)
-                return float(((0.5 * (q5[1] ** 2 + q5[2] ** 2 + q5[3] ** 2) / q5[0]) * wJ).sum() / wJ.sum())
+                u2 = (q5[1] ** 2 + q5[2] ** 2 + q5[3] ** 2) / q5[0] ** 2
+                return q5, u2, (gam - 1.0) * (q5[4] - 0.5 * q5[0] * u2)
+
+            def kinetic(qq):
+                q5, u2, _ = prim(qq)
+                return float(((0.5 * q5[0] * u2) * wJ).sum() / wJ.sum())
 
             def healthy(qq):
-                q5 = qq.reshape(5, -1)
-                pr_ = (1.4 - 1.0) * (q5[4] - 0.5 * (q5[1] ** 2 + q5[2] ** 2 + q5[3] ** 2) / q5[0])
+                q5, _, pr_ = prim(qq)
                 return bool(torch.isfinite(q5).all()) and bool((q5[0] > 0).all()) and bool((pr_ > 0).all())
+
+            def speed_max(qq):
+                q5, u2, pr_ = prim(qq)
+                return float((torch.sqrt(u2) + torch.sqrt(gam * pr_ / q5[0])).max())
 
             qs = [b[1].reshape(-1).clone() for b in built]
             ek0 = kinetic(qs[0])
             alive = [0, 1, 2]
             fail = {}
-            done = 0
+            t = 0.0
+            steps = 0
+            dts = []
             t0 = time.time()
             ps, qcat, key = None, None, None
-            while done < n_total and alive:
+            while t < t_final * (1.0 - 1e-12) and alive:
                 if key != tuple(alive):
                     key = tuple(alive)
                     ps = P.ProblemSet([built[i][0] for i in alive])
                     qcat = torch.cat([qs[i] for i in alive])
-                    dts = torch.full((len(alive),), dt, dtype=torch.float64, device=dev)
-                n = min(chunk, n_total - done)
-                ps.rk_step(qcat, dts, n)
+                dt = cfl * h / ((p + 1) ** 2 * max(speed_max(qs[i]) for i in alive))
+                n = int(math.ceil((t_final - t) / dt))
+                if n > chunk:
+                    n = chunk
+                else:
+                    dt = (t_final - t) / n
+                dts.append(dt)
+                dtd = torch.full((len(alive),), dt, dtype=torch.float64, device=dev)
+                ps.rk_step(qcat, dtd, n)
                 try:
                     ps.status()
                 except P.SBPError:
                     pass
-                done += n
-                if done % (10 * chunk) == 0:
-                    print(f"robustness E={E} p={p}: step {done}/{n_total}", file=sys.stderr, flush=True)
+                t += n * dt
+                steps += n
+                if steps % (10 * chunk) == 0:
+                    print(f"robustness E={E} p={p}: t = {t:.3f}, {steps} steps", file=sys.stderr, flush=True)
                 off = 0
                 for i in list(alive):
                     m = qs[i].numel()
                     qs[i] = qcat[off:off + m]
                     off += m
                     if not healthy(qs[i]):
-                        fail[i] = done * dt
+                        fail[i] = t
                 for i in fail:
                     if i in alive:
                         alive.remove(i)
                         qs[i] = qs[i].clone()
             secs = time.time() - t0
             for i, (name, _) in enumerate(schemes):
-                r = {"E": E, "p": p, "scheme": name, "steps": n_total, "dt": dt}
+                r = {"E": E, "p": p, "scheme": name, "steps": steps, "dt_min": min(dts), "dt_max": max(dts)}
                 if i in fail:
                     r.update(result="failure", t_fail_before=round(fail[i], 4))
                 else:
                     r.update(result="success", kinetic_energy_ratio=round(kinetic(qs[i]) / ek0, 5))
                 out["results"].append(r)
-            print(f"robustness E={E} p={p}: steps {n_total}, {secs:.1f} s, failed "
+            print(f"robustness E={E} p={p}: steps {steps}, {secs:.1f} s, failed "
                   f"{[schemes[i][0] for i in sorted(fail)]}", file=sys.stderr, flush=True)
             print(json.dumps({"tgv_robustness_run": out["results"][-len(schemes):]}), file=sys.stderr,
                   flush=True)
