@@ -135,6 +135,36 @@ int sbp_lgl_operator(int32_t p, double *x, double *w, double *D);
 int sbp_metrics(int32_t p, int64_t n_elem, const double *coords, double *metric, double *jac,
                 void *stream);
 
+/* Optimised metric terms (the paragraph after eq. discGCLconvection: analytic metrics on the faces,
+ * and volume metrics that satisfy the discrete GCL while staying as close as possible to the
+ * analytic ones), for meshes whose faces are aligned and conforming.  Steps:
+ * 1. analytic metrics J dxi_l/dx_m = (a_{l+1} x a_{l+2})_m and J = a_1 . (a_2 x a_3) from the
+ *    covariant vectors a_i = dx/dxi_i at the nodes;
+ * 2. the face-normal components (J dxi_l/dx_m on the faces normal to xi_l) take one value per face
+ *    node, the mean of the two elements' analytic values, corrected by the least-norm amount (2-norm
+ *    over all face nodes of the mesh) for which every element can satisfy the GCL: with those values
+ *    held, the GCL of an element has a solution only if 7 linear combinations of its face values
+ *    vanish (tensor products of the LGL weights and of the left null vector of D; the all-weights
+ *    one is the closure of the element's surface);
+ * 3. per element and m, the other entries move by the least-norm amount (2-norm) that makes
+ *    sum_l D_l [J dxi_l/dx_m] vanish at every node.
+ * The result satisfies eq. discGCLconvection to rounding, both elements of a face store identical
+ * face-normal values, and on affine elements it equals the analytic metrics.
+ * p: 2..SBP_MAX_P; nbr: device int32 [K][6] as in sbp_problem (negative entries are boundary
+ * faces; every non-negative entry must name an element whose opposite face names this element
+ * back, i.e. no face_orient rotations); dxdxi: device SoA [9][K*N^3], entry 3*m + i is dx_m/dxi_i
+ * (0-based) at the node, e.g. the closed-form derivative of the mapping; metric: device [9][K*N^3]
+ * out, as for sbp_metrics; jac: device [K*N^3] out (the analytic J).  All arrays are owned by the
+ * caller; metric and jac must not overlap the inputs.
+ * The call is synchronous: it reads the neighbour table on the host, allocates temporary device
+ * memory (about (18 N^2 + 90) doubles per element) and waits for the stream before returning.
+ * Returns SBP_ERR_DEGREE for p outside [2, SBP_MAX_P], SBP_ERR_ARG for bad sizes or pointers,
+ * SBP_ERR_MESH for a neighbour entry >= K or a face that is not paired back (and if the face
+ * compatibility system does not converge, which does not happen on valid meshes), SBP_ERR_HIP for
+ * runtime errors. */
+int sbp_metrics_optimized(int32_t p, int64_t n_elem, const int32_t *nbr, const double *dxdxi,
+                          double *metric, double *jac, void *stream);
+
 /* Device workspace (bytes) needed by sbp_residual, sbp_rk_step and sbp_residual_vjp for this
  * problem set.  0 on invalid arguments. */
 size_t sbp_workspace_bytes(const sbp_problem *probs, int32_t n_prob);

@@ -26,7 +26,8 @@ SBP_BC_ADIABATIC_WALL = -3
 EXPORTED = ("sbp_version", "sbp_error_string", "sbp_lgl_operator", "sbp_metrics",
             "sbp_workspace_bytes", "sbp_residual", "sbp_rk_step", "sbp_residual_vjp",
             "sbp_profile_residual", "sbp_autotune", "sbp_schedule_count", "sbp_set_schedule",
-            "sbp_status", "sbp_release", "sbp_residual_noalloc", "sbp_profile_collect")
+            "sbp_status", "sbp_release", "sbp_residual_noalloc", "sbp_profile_collect",
+            "sbp_metrics_optimized")
 
 
 class sbp_problem(ctypes.Structure):
@@ -74,6 +75,7 @@ def lib():
         L.sbp_error_string.restype = ctypes.c_char_p
         L.sbp_lgl_operator.argtypes = [i32, dp, dp, dp]
         L.sbp_metrics.argtypes = [i32, i64, vp, vp, vp, vp]
+        L.sbp_metrics_optimized.argtypes = [i32, i64, vp, vp, vp, vp, vp]
         L.sbp_workspace_bytes.argtypes = [P, i32]
         L.sbp_workspace_bytes.restype = sz
         L.sbp_residual.argtypes = [P, i32, vp, vp, vp, sz, vp]

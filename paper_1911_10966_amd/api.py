@@ -64,6 +64,30 @@ def metrics(p: int, coords: torch.Tensor):
     return metric, jac
 
 
+def metrics_optimized(p: int, nbr: torch.Tensor, dxdxi: torch.Tensor):
+    """Optimised metric terms (9, nodes) and Jacobian (nodes,) from the mapping derivative at the
+    nodes (9, nodes), entry 3 m + i = dx_m/dxi_i, on the aligned conforming mesh of the neighbour
+    table nbr (K, 6): analytic face values corrected so that every element can meet the discrete
+    GCL, then the least-norm volume correction that meets it."""
+    N3 = (p + 1) ** 3
+    if dxdxi.numel() == 0 or dxdxi.numel() % (9 * N3) != 0:
+        raise ValueError(f"dxdxi has {dxdxi.numel()} entries, not a positive multiple of "
+                         f"9 (p+1)^3 = {9 * N3}")
+    _need(dxdxi, F64, "dxdxi")
+    nodes = dxdxi.numel() // 9
+    K = nodes // N3
+    _need(nbr, torch.int32, "nbr")
+    if nbr.numel() != 6 * K:
+        raise ValueError(f"nbr has {nbr.numel()} entries, expected 6 K = {6 * K}")
+    if nbr.device != dxdxi.device:
+        raise ValueError("nbr and dxdxi are on different devices")
+    metric = torch.empty((9, nodes), dtype=F64, device=dxdxi.device)
+    jac = torch.empty((nodes,), dtype=F64, device=dxdxi.device)
+    check(lib().sbp_metrics_optimized(p, K, _ptr(nbr), _ptr(dxdxi), _ptr(metric), _ptr(jac),
+                                      _stream()), "sbp_metrics_optimized")
+    return metric, jac
+
+
 @dataclass
 class Problem:
     """One problem on the device: degree, element count, neighbour table (negative entries are

@@ -12,7 +12,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbp_hip.so")
-SOURCES = ["sbp_kernels.hip", "sbp_planes.hip", "sbp_vjp.hip", "sbp_noalloc.hip", "sbp_capi.cpp"]
+SOURCES = ["sbp_kernels.hip", "sbp_planes.hip", "sbp_vjp.hip", "sbp_noalloc.hip", "sbp_optmetrics.hip",
+           "sbp_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # packed FP32 instructions stay disabled in all device code

@@ -2,6 +2,8 @@
 // the 1-D LGL operator, workspace layout, launch sequencing and the RK4 graph cache.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -125,6 +127,96 @@ const double *device_D(int p) {
         it = tables.emplace(dev, buf).first;
     }
     return it->second + 256 * p;
+}
+
+// Eigen-decomposition of a symmetric n x n matrix (row-major) by cyclic Jacobi rotations:
+// A = V diag(lam) V^T with V[i * n + k] the i-th component of eigenvector k.
+void sym_eigen(int n, std::vector<long double> A, std::vector<long double> &V,
+               std::vector<long double> &lam) {
+    V.assign(n * n, 0.0L);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0L;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        long double off = 0.0L, diag = 0.0L;
+        for (int i = 0; i < n; ++i) {
+            diag += A[i * n + i] * A[i * n + i];
+            for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+        }
+        if (off <= 1e-40L * diag) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const long double apq = A[p * n + q];
+                if (apq == 0.0L) continue;
+                // rotation in the (p, q) plane that zeroes A[p][q]: t = tan(phi) is the smaller
+                // root of t^2 + 2 theta t - 1 = 0
+                const long double theta = (A[q * n + q] - A[p * n + p]) / (2.0L * apq);
+                const long double t = (theta >= 0.0L ? 1.0L : -1.0L) /
+                                      (std::fabs(theta) + std::sqrt(theta * theta + 1.0L));
+                const long double c = 1.0L / std::sqrt(t * t + 1.0L), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // A <- A R
+                    const long double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - sn * akq;
+                    A[k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- R^T A
+                    const long double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - sn * aqk;
+                    A[q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {  // V <- V R
+                    const long double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - sn * vkq;
+                    V[k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    lam.assign(n, 0.0L);
+    for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
+}
+
+// Tables of the optimised metric terms for degree p (declared in sbp_internal.h).  B has rank
+// N - 2 (D restricted to the interior nodes is injective), so its two smallest eigenvalues are the
+// null pair; the eigen-decomposition is checked against B before use.  The left null vector of D
+// is z_i = w_i P_p(x_i): sum_i w_i P_p(x_i) l_j'(x_i) is the exact quadrature of P_p l_j', a
+// polynomial of degree 2p - 1, and P_p is orthogonal to every polynomial of degree p - 1.
+bool opt_metric_tables(int p, sbp::OptMetricTables &t) {
+    std::vector<long double> x, w, D;
+    lgl_ld(p, x, w, D);
+    const int N = p + 1;
+    std::vector<long double> B(N * N, 0.0L), V, lam;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            long double acc = 0.0L;
+            for (int k = 1; k < N - 1; ++k) acc += D[i * N + k] * D[j * N + k];
+            B[i * N + j] = acc;
+        }
+    sym_eigen(N, B, V, lam);
+    long double bmax = 0.0L, resid = 0.0L;
+    for (int i = 0; i < N * N; ++i) bmax = std::max(bmax, std::fabs(B[i]));
+    for (int i = 0; i < N; ++i)
+        for (int k = 0; k < N; ++k) {
+            long double acc = 0.0L;
+            for (int j = 0; j < N; ++j) acc += B[i * N + j] * V[j * N + k];
+            resid = std::max(resid, std::fabs(acc - lam[k] * V[i * N + k]));
+        }
+    if (!(resid <= 1e-14L * bmax)) return false;
+    int lo0 = 0;
+    for (int k = 1; k < N; ++k)
+        if (lam[k] < lam[lo0]) lo0 = k;
+    int lo1 = lo0 == 0 ? 1 : 0;
+    for (int k = 0; k < N; ++k)
+        if (k != lo0 && lam[k] < lam[lo1]) lo1 = k;
+    t = sbp::OptMetricTables{};
+    t.p = p;
+    t.null_mask = (1 << lo0) | (1 << lo1);
+    for (int i = 0; i < N * N; ++i) { t.D[i] = (double)D[i]; t.V[i] = (double)V[i]; }
+    for (int k = 0; k < N; ++k) t.lam[k] = ((t.null_mask >> k) & 1) ? 0.0 : (double)lam[k];
+    for (int i = 0; i < N; ++i) {
+        long double P, dP;
+        legendre_ld(p, x[i], P, dP);
+        t.pat[0][i] = (double)(w[i] * P);
+        t.pat[1][i] = (double)w[i];
+    }
+    return true;
 }
 
 bool aligned8(const void *p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % 8) == 0; }
@@ -530,6 +622,44 @@ int sbp_metrics(int32_t p, int64_t n_elem, const double *coords, double *metric,
     if (!D) return SBP_ERR_HIP;
     return sbp::launch_metrics(p, n_elem, coords, metric, jac, D, (hipStream_t)stream) == 0
                ? SBP_OK : SBP_ERR_HIP;
+}
+
+int sbp_metrics_optimized(int32_t p, int64_t n_elem, const int32_t *nbr, const double *dxdxi,
+                          double *metric, double *jac, void *stream) {
+    if (p < 2 || p > SBP_MAX_P) return SBP_ERR_DEGREE;
+    if (n_elem <= 0 || nbr == nullptr || (reinterpret_cast<uintptr_t>(nbr) % 4) != 0 ||
+        !aligned8(dxdxi) || !aligned8(metric) || !aligned8(jac))
+        return SBP_ERR_ARG;
+    const int N = p + 1;
+    if (n_elem > (int64_t)INT32_MAX || n_elem > (int64_t)(INT64_MAX / (18LL * N * N * N)))
+        return SBP_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    // aligned conforming faces: every neighbour names this element back across the opposite face
+    std::vector<int32_t> h(n_elem * 6);
+    if (hipMemcpyAsync(h.data(), nbr, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return SBP_ERR_HIP;
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int32_t nb = h[e * 6 + f];
+            if (nb >= n_elem) return SBP_ERR_MESH;
+            if (nb >= 0 && h[(int64_t)nb * 6 + (f ^ 1)] != e) return SBP_ERR_MESH;
+        }
+    static std::mutex mu;
+    static sbp::OptMetricTables tabs[SBP_MAX_P + 1];
+    static bool built[SBP_MAX_P + 1] = {};
+    sbp::OptMetricTables t;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!built[p]) {
+            if (!opt_metric_tables(p, tabs[p])) return SBP_ERR_DEGREE;
+            built[p] = true;
+        }
+        t = tabs[p];
+    }
+    const int rc = sbp::optimized_metrics(t, n_elem, nbr, dxdxi, metric, jac, s);
+    return rc == 0 ? SBP_OK : (rc == 2 ? SBP_ERR_MESH : SBP_ERR_HIP);
 }
 
 size_t sbp_workspace_bytes(const sbp_problem *probs, int32_t n_prob) {

@@ -155,4 +155,20 @@ int launch_vjp(int p, const VjpArgs &a, hipStream_t s);
 int launch_metrics(int p, long long K, const double *x, double *metric, double *jac,
                    const double *D, hipStream_t s);
 
+// Optimised metric terms (reading of the metric-terms paragraph after eq. discGCLconvection):
+// analytic metrics from the mapping derivative, face-normal values corrected by the least-norm
+// amount that meets every element's compatibility conditions, then the other entries moved by the
+// least-norm amount that satisfies the discrete GCL.  The host supplies the degree's tables.
+struct OptMetricTables {
+    int p;
+    double D[256];      // collocation derivative, row-major
+    double V[256];      // V[i * N + k]: component i of the k-th eigenvector of B = D diag(0,1..1,0) D^T
+    double lam[16];     // eigenvalues of B; exactly 0 on its two-dimensional null space
+    int null_mask;      // bit k set: eigenvector k belongs to that null space
+    double pat[2][16];  // face patterns: [0] the left null vector of D, [1] the LGL weights
+};
+// 0 on success, 1 on a HIP error, 2 when the compatibility system did not converge.
+int optimized_metrics(const OptMetricTables &t, long long K, const int32_t *nbr,
+                      const double *dxdxi, double *metric, double *jac, hipStream_t s);
+
 }  // namespace sbp

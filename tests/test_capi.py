@@ -169,3 +169,20 @@ def test_noalloc_rejects_oversize_sets_and_bad_arguments_on_host():
     assert L.sbp_residual_noalloc(ok, 1, 64, 128, None, None) == _lib.SBP_ERR_ARG      # no status word
     assert L.sbp_residual_noalloc(ok, 1, 64, 64, 256, None) == _lib.SBP_ERR_ARG        # aliasing output
     assert L.sbp_residual_noalloc(_prob(p=16), 1, 64, 128, 256, None) == _lib.SBP_ERR_DEGREE
+
+
+def test_optimized_metrics_rejects_bad_degree_and_arguments_on_host():
+    """Checked before the neighbour table is read or any device work starts (fake aligned
+    addresses are never dereferenced)."""
+    import torch
+    L = P.lib()
+    for p in (1, _lib.SBP_MAX_P + 1):
+        assert L.sbp_metrics_optimized(p, 8, 64, 128, 256, 512, None) == _lib.SBP_ERR_DEGREE
+    assert L.sbp_metrics_optimized(3, 0, 64, 128, 256, 512, None) == _lib.SBP_ERR_ARG
+    assert L.sbp_metrics_optimized(3, 8, None, 128, 256, 512, None) == _lib.SBP_ERR_ARG
+    assert L.sbp_metrics_optimized(3, 8, 64, 129, 256, 512, None) == _lib.SBP_ERR_ARG
+    assert L.sbp_metrics_optimized(3, 8, 66, 128, 256, 512, None) == _lib.SBP_ERR_ARG
+    with pytest.raises(ValueError, match="multiple"):
+        P.metrics_optimized(2, torch.zeros(6, dtype=torch.int32), torch.zeros(9 * 27 + 9, dtype=torch.float64))
+    with pytest.raises(ValueError, match="device tensor"):
+        P.metrics_optimized(2, torch.zeros(6, dtype=torch.int32), torch.zeros(9 * 27, dtype=torch.float64))
