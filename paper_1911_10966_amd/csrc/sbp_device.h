@@ -183,6 +183,39 @@ __device__ __forceinline__ void flux_n(const Node &a, const Node &b, double n0, 
     }
 }
 
+// Chandrashekar flux contracted with (n0, n1, n2) for the volume pair loop, from node data held as
+// halves: rho/2, U/2 and |U|^2/4 (beta and the logarithms in full).  A sum of two halves is the
+// arithmetic mean, exactly (scaling by 2 commutes with rounding), and every other quantity below is
+// the one of flux_n<0> up to an exact power-of-2 factor, so the result equals flux_n<0> for the full
+// values bit for bit, with six multiplications by 1/2 and one doubling fewer.  igm1 = 1/(gamma-1).
+__device__ __forceinline__ void flux_pair_half(const Node &a, const Node &b, double n0, double n1,
+                                               double n2, double igm1, double f[5]) {
+    const double ub1 = a.u1 + b.u1, ub2 = a.u2 + b.u2, ub3 = a.u3 + b.u3;
+    const double un = ub1 * n0 + ub2 * n1 + ub3 * n2;
+    const double rb = a.rho + b.rho, dr = a.rho - b.rho;  // mean density, half the difference
+    const double sb = a.beta + b.beta, db = a.beta - b.beta;
+    const double irb = rcp(rb * sb);
+    const double isr = sb * irb;  // 1 / mean density
+    const double isb = rb * irb;  // 1 / (beta_i + beta_j)
+    const double zr = dr * isr, ur = zr * zr;
+    double rho_hat;
+    if (ur < LOGMEAN_U) rho_hat = rb * series_G(ur);
+    else rho_hat = (dr + dr) * rcp(a.lrho - b.lrho);
+    const double zb = db * isb, ub = zb * zb;
+    double ib;  // half the inverse logarithmic mean of beta
+    if (ub < LOGMEAN_U) ib = isb * series_F(ub);
+    else ib = (0.5 * (a.lbeta - b.lbeta)) * rcp(db);
+    const double pt = rb * isb;  // rho_bar / (2 beta_bar)
+    const double fr = rho_hat * un;
+    f[0] = fr;
+    f[1] = fma(fr, ub1, pt * n0);
+    f[2] = fma(fr, ub2, pt * n1);
+    f[3] = fma(fr, ub3, pt * n2);
+    const double kh = a.k + b.k;  // half the mean of |U|^2
+    const double ubsq = ub1 * ub1 + ub2 * ub2 + ub3 * ub3;
+    f[4] = fma(fr, igm1 * ib - kh + ubsq, pt * un);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Map dispatch
 // slot b to a virtual block so that every XCD walks one contiguous range of elements: face
 // neighbours of an element are then mostly resident in the same L2.
@@ -513,14 +546,16 @@ __device__ __forceinline__ void face_terms(const ResArgs &a, const FaceOwn &ow, 
         const double iTi = 2.0 * a.R * mi.beta, iTn = 2.0 * a.R * o.beta;
         const double wi[4] = {mi.u1 * iTi, mi.u2 * iTi, mi.u3 * iTi, -iTi};
         const double wn[4] = {o.u1 * iTn, o.u2 * iTn, o.u3 * iTn, -iTn};
-        const double ct = 0.5 * s * isw;
+        const double mct = -0.5 * s * isw;
+        double dw[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[5 + c] = ct * (wn[c] - wi[c]);
+        for (int c = 0; c < 4; ++c) {
+            dw[c] = wi[c] - wn[c];
+            v[5 + c] = mct * dw[c];  // (s / (2 w_end)) (w_nu - w_i)
+        }
         if (a.eta != 0.0) {
             const double iJn = rcp(nb.J);
-            double dw[4], pi_[4], pn_[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) dw[c] = wi[c] - wn[c];
+            double pi_[4], pn_[4];
             visc_flux_rank1(Ai[0], Ai[1], Ai[2], iJi, dw, mi.u1, mi.u2, mi.u3, ow.T, a.mu, a.kap, pi_);
             visc_flux_rank1(An0, An1, An2, iJn, dw, o.u1, o.u2, o.u3, rcp(iTn), a.mu, a.kap, pn_);
             const double cf = -0.5 * a.eta * isw;

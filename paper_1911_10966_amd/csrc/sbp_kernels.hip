@@ -19,16 +19,37 @@ namespace {
 // the interface work items (6 N^2 x 9 or x 5 per element) reuse the fields from 8 on.
 constexpr int tile_fields(bool visc) { return visc ? 24 : 20; }
 
+// Doubles between consecutive LDS fields: the node count rounded up to a multiple of 64 when that
+// costs at most 5% more LDS.  Fields then lie a multiple of 512 bytes apart, so the reads of all
+// fields of one node pair up in ds_read2st64 instructions from a single address.
+constexpr int field_stride(int nodes) {
+    const int r = (nodes + 63) / 64 * 64;
+    return (r - nodes) * 20 <= nodes ? r : nodes;
+}
+
 // Element size from which the interface terms run as (face, face node) work items.
 constexpr int kFaceItemsFrom = 6;
+
+// D along the cyclic pairing of the pair loop, row-major in (round, node index i): rows
+// r - 1 = 0 .. N/2 - 1 hold D(i, i + r), rows N/2 + r - 1 hold D(i, i - r) (indices mod N), so
+// that a round reads its weights at a constant offset from the node's own index.
+template <int N>
+constexpr int kRotRows = N / 2 + (N - 1) / 2;
+template <int N>
+__device__ __forceinline__ double rotated_D(const double *D, int t) {
+    const int row = t / N, i = t - row * N;
+    const int j = row < N / 2 ? (i + row + 1) % N : (i - (row - N / 2 + 1) + N) % N;
+    return D[i * N + j];
+}
 
 // One tile of EPW elements (first element ebase) of one problem; all threads of the block call it.
 // MD: matrix interface dissipation (iface_diss = 2) instead of Lax-Friedrichs.  OR: the problem has
 // a face-orientation table (unstructured faces); without it the aligned partners are compiled in.
 template <int N, int EPW, bool VISC, int FLUX, bool MD, bool OR>
 __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase, double *s_buf,
-                                              const double *s_D, int *s_face) {
+                                              const double *s_D, const double *s_Dr, int *s_face) {
     constexpr int N2 = N * N, N3 = N * N * N, NODES = EPW * N3;
+    constexpr int FS = field_stride(NODES);
     constexpr bool COMPACT = !VISC;  // see tile_fields
     constexpr int LDS_FIELDS = tile_fields(VISC);
     constexpr int F_RHO = 0, F_U1 = 1, F_U2 = 2, F_U3 = 3, F_B = 4, F_LR = 5, F_LB = 6;
@@ -73,15 +94,25 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     bool ok;
     primitives(q, gm1, me, Pme, ok);
     if (active && !ok) atomicOr(a.status, FLAG_NONPHYSICAL);
+    // The entropy-conservative pair loop works on halves (flux_pair_half): rho, U and |U|^2 of the
+    // node are scaled by 1/2, 1/2 and 1/4 here, staged so, and scaled back exactly after the loop.
+    constexpr bool HALF = (FLUX == 0);
+    if constexpr (HALF) {
+        me.rho *= 0.5;
+        me.u1 *= 0.5;
+        me.u2 *= 0.5;
+        me.u3 *= 0.5;
+        me.k *= 0.25;
+    }
     if (tid < NODES) {
-        s_buf[F_RHO * NODES + tid] = me.rho;
-        s_buf[F_U1 * NODES + tid] = me.u1;
-        s_buf[F_U2 * NODES + tid] = me.u2;
-        s_buf[F_U3 * NODES + tid] = me.u3;
-        s_buf[F_B * NODES + tid] = me.beta;
-        s_buf[F_LR * NODES + tid] = me.lrho;
-        s_buf[F_LB * NODES + tid] = me.lbeta;
-        if constexpr (!COMPACT) s_buf[F_K * NODES + tid] = me.k;
+        s_buf[F_RHO * FS + tid] = me.rho;
+        s_buf[F_U1 * FS + tid] = me.u1;
+        s_buf[F_U2 * FS + tid] = me.u2;
+        s_buf[F_U3 * FS + tid] = me.u3;
+        s_buf[F_B * FS + tid] = me.beta;
+        s_buf[F_LR * FS + tid] = me.lrho;
+        s_buf[F_LB * FS + tid] = me.lbeta;
+        if constexpr (!COMPACT) s_buf[F_K * FS + tid] = me.k;
     }
     // neighbour index and kind of the tile's faces, decoded once per face (visible to all threads
     // after the first barrier below); a mesh error is flagged here
@@ -112,7 +143,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 double f[5];
                 euler_flux_n(me, Pme, q[4], A[l][0], A[l][1], A[l][2], f);
 #pragma unroll
-                for (int c = 0; c < 5; ++c) s_buf[(F_MSG0 + c) * NODES + tid] = f[c];
+                for (int c = 0; c < 5; ++c) s_buf[(F_MSG0 + c) * FS + tid] = f[c];
             }
             __syncthreads();
             if (tid < NODES) {
@@ -122,13 +153,14 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     const double dd = s_D[il * N + b];
                     const int pn = tid + (b - il) * stride[l];
 #pragma unroll
-                    for (int c = 0; c < 5; ++c) acc[c] = fma(-dd, s_buf[(F_MSG0 + c) * NODES + pn], acc[c]);
+                    for (int c = 0; c < 5; ++c) acc[c] = fma(-dd, s_buf[(F_MSG0 + c) * FS + pn], acc[c]);
                 }
             }
             __syncthreads();
         }
     } else {
         int round = 0;
+        const double igm1 = 1.0 / gm1;
     #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int fa = (l & 1) ? F_A1 : F_A0;
@@ -137,9 +169,9 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 if (l > 0) __syncthreads();
             }
             if (tid < NODES) {
-                s_buf[(fa + 0) * NODES + tid] = A[l][0];
-                s_buf[(fa + 1) * NODES + tid] = A[l][1];
-                s_buf[(fa + 2) * NODES + tid] = A[l][2];
+                s_buf[(fa + 0) * FS + tid] = A[l][0];
+                s_buf[(fa + 1) * FS + tid] = A[l][1];
+                s_buf[(fa + 2) * FS + tid] = A[l][2];
             }
             __syncthreads();
             const int il = idx[l];
@@ -147,19 +179,20 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             auto pair = [&](int b, double f[5]) {
                 const int pn = tid + (b - il) * st;
                 Node o;
-                o.rho = s_buf[F_RHO * NODES + pn];
-                o.u1 = s_buf[F_U1 * NODES + pn];
-                o.u2 = s_buf[F_U2 * NODES + pn];
-                o.u3 = s_buf[F_U3 * NODES + pn];
-                o.beta = s_buf[F_B * NODES + pn];
-                o.lrho = s_buf[F_LR * NODES + pn];
-                o.lbeta = s_buf[F_LB * NODES + pn];
+                o.rho = s_buf[F_RHO * FS + pn];
+                o.u1 = s_buf[F_U1 * FS + pn];
+                o.u2 = s_buf[F_U2 * FS + pn];
+                o.u3 = s_buf[F_U3 * FS + pn];
+                o.beta = s_buf[F_B * FS + pn];
+                o.lrho = s_buf[F_LR * FS + pn];
+                o.lbeta = s_buf[F_LB * FS + pn];
                 if constexpr (COMPACT) o.k = fma(o.u1, o.u1, fma(o.u2, o.u2, o.u3 * o.u3));
-                else o.k = s_buf[F_K * NODES + pn];
-                const double n0 = A[l][0] + s_buf[(fa + 0) * NODES + pn];
-                const double n1 = A[l][1] + s_buf[(fa + 1) * NODES + pn];
-                const double n2 = A[l][2] + s_buf[(fa + 2) * NODES + pn];
-                flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
+                else o.k = s_buf[F_K * FS + pn];
+                const double n0 = A[l][0] + s_buf[(fa + 0) * FS + pn];
+                const double n1 = A[l][1] + s_buf[(fa + 1) * FS + pn];
+                const double n2 = A[l][2] + s_buf[(fa + 2) * FS + pn];
+                if constexpr (HALF) flux_pair_half(me, o, n0, n1, n2, igm1, f);
+                else flux_n<FLUX>(me, o, n0, n1, n2, gm1, f);
                 return pn;
             };
     #pragma unroll
@@ -171,17 +204,19 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 if (tid < NODES) {
                     double f[5];
                     const int pn = pair(b, f);
-                    const double dab = s_D[il * N + b], dba = s_D[b * N + il];
+                    const double dab = s_Dr[(r - 1) * N + il];  // D(i, i + r)
     #pragma unroll
                     for (int c = 0; c < 5; ++c) {
                         acc[c] = fma(-dab, f[c], acc[c]);
-                        s_buf[(fm + c) * NODES + pn] = dba * f[c];
+                        s_buf[(fm + c) * FS + pn] = f[c];
                     }
                 }
                 __syncthreads();
                 if (tid < NODES) {
+                    // the pair flux posted by the node r places back: weight D(i, i - r)
+                    const double dba = s_Dr[(N / 2 + r - 1) * N + il];
     #pragma unroll
-                    for (int c = 0; c < 5; ++c) acc[c] -= s_buf[(fm + c) * NODES + tid];
+                    for (int c = 0; c < 5; ++c) acc[c] = fma(-dba, s_buf[(fm + c) * FS + tid], acc[c]);
                 }
             }
             if constexpr (N % 2 == 0) {
@@ -190,13 +225,20 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     if (b >= N) b -= N;
                     double f[5];
                     pair(b, f);
-                    const double dab = s_D[il * N + b];
+                    const double dab = s_Dr[(N / 2 - 1) * N + il];
     #pragma unroll
                     for (int c = 0; c < 5; ++c) acc[c] = fma(-dab, f[c], acc[c]);
                 }
             }
         }
         __syncthreads();
+        if constexpr (HALF) {
+            me.rho *= 2.0;
+            me.u1 *= 2.0;
+            me.u2 *= 2.0;
+            me.u3 *= 2.0;
+            me.k *= 4.0;
+        }
     }
 
     const double iJ = rcp(J);
@@ -216,7 +258,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         constexpr int FACE_ITEMS = EPW * 6 * N2;
         constexpr int NV = VISC ? 9 : 5;
         static_assert(NV * 6 <= (LDS_FIELDS - 8) * N, "face slots exceed the LDS tile");
-        double *fsl = s_buf + 8 * NODES;  // [NV][FACE_ITEMS]
+        double *fsl = s_buf + 8 * FS;  // [NV][FACE_ITEMS]
         // at most two items per thread, as straight-line code (a loop here keeps both items' values
         // live and costs a third of the register file)
         static_assert(FACE_ITEMS <= 2 * NT, "at most two face items per thread");
@@ -254,16 +296,17 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 for (int c = 0; c < 5; ++c) qi[c] = a.q[c * nodes + go];
 #pragma unroll
                 for (int m = 0; m < 3; ++m) Ai[m] = a.metric[(3 * l + m) * nodes + go];
-                Node mi;
-                mi.rho = s_buf[F_RHO * NODES + pl];
-                mi.u1 = s_buf[F_U1 * NODES + pl];
-                mi.u2 = s_buf[F_U2 * NODES + pl];
-                mi.u3 = s_buf[F_U3 * NODES + pl];
-                mi.beta = s_buf[F_B * NODES + pl];
-                mi.lrho = s_buf[F_LR * NODES + pl];
-                mi.lbeta = s_buf[F_LB * NODES + pl];
+                Node mi;  // the staged node data (halves of rho, U, |U|^2 for the ES-C pair loop)
+                constexpr double H = HALF ? 2.0 : 1.0;
+                mi.rho = H * s_buf[F_RHO * FS + pl];
+                mi.u1 = H * s_buf[F_U1 * FS + pl];
+                mi.u2 = H * s_buf[F_U2 * FS + pl];
+                mi.u3 = H * s_buf[F_U3 * FS + pl];
+                mi.beta = s_buf[F_B * FS + pl];
+                mi.lrho = s_buf[F_LR * FS + pl];
+                mi.lbeta = s_buf[F_LB * FS + pl];
                 if constexpr (COMPACT) mi.k = fma(mi.u1, mi.u1, fma(mi.u2, mi.u2, mi.u3 * mi.u3));
-                else mi.k = s_buf[F_K * NODES + pl];
+                else mi.k = (H * H) * s_buf[F_K * FS + pl];
                 const double Pi = gm1 * (qi[4] - 0.5 * qi[0] * mi.k);
                 const double iJi = (VISC && a.eta != 0.0) ? rcp(a.jac[go]) : 1.0;
                 face_terms<FLUX, VISC, MD>(a, face_own(a, mi, Pi, qi, iJi), Ai, pg, kind, lp, sg,
@@ -326,7 +369,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 for (int c = 0; c < 5; ++c) acc[c] += v[c];
                 if constexpr (VISC) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) s_buf[(8 + 4 * l + c) * NODES + tid] = v[5 + c];
+                    for (int c = 0; c < 4; ++c) s_buf[(8 + 4 * l + c) * FS + tid] = v[5 + c];
                 }
             }
         }
@@ -340,7 +383,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
         const double w[4] = {me.u1 * iT, me.u2 * iT, me.u3 * iT, -iT};
         if (tid < NODES) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s_buf[c * NODES + tid] = w[c];
+            for (int c = 0; c < 4; ++c) s_buf[c * FS + tid] = w[c];
         }
         __syncthreads();
 #pragma unroll
@@ -353,10 +396,10 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     const int side = idx[d] == N - 1 ? 1 : 0;
                     const int it = (slot * 6 + 2 * d + side) * N2 + tangential_index<N>(d, i1, i2, i3);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) th[d][c] = s_buf[8 * NODES + (5 + c) * FACE_ITEMS + it];
+                    for (int c = 0; c < 4; ++c) th[d][c] = s_buf[8 * FS + (5 + c) * FACE_ITEMS + it];
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) th[d][c] = s_buf[(8 + 4 * d + c) * NODES + tid];
+                    for (int c = 0; c < 4; ++c) th[d][c] = s_buf[(8 + 4 * d + c) * FS + tid];
                 }
             }
             if (tid < NODES) {
@@ -366,7 +409,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     const double dd = s_D[il * N + b];
                     const int pn = tid + (b - il) * stride[d];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) th[d][c] = fma(dd, s_buf[c * NODES + pn], th[d][c]);
+                    for (int c = 0; c < 4; ++c) th[d][c] = fma(dd, s_buf[c * FS + pn], th[d][c]);
                 }
             }
         }
@@ -414,7 +457,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
             __syncthreads();
             if (tid < NODES) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) s_buf[(4 + c) * NODES + tid] = fh[l][c];
+                for (int c = 0; c < 4; ++c) s_buf[(4 + c) * FS + tid] = fh[l][c];
             }
             __syncthreads();
             if (tid < NODES) {
@@ -424,7 +467,7 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     const double dd = s_D[il * N + b];
                     const int pn = tid + (b - il) * stride[l];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(dd, s_buf[(4 + c) * NODES + pn], acc[c + 1]);
+                    for (int c = 0; c < 4; ++c) acc[c + 1] = fma(dd, s_buf[(4 + c) * FS + pn], acc[c + 1]);
                 }
             }
         }
@@ -449,21 +492,25 @@ __global__ void __launch_bounds__(NT_OF(EPW * N * N * N))
 __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
 k_residual(const GroupArgs g) {
     constexpr int N2 = N * N, NODES = EPW * N * N * N;
-    __shared__ double s_buf[tile_fields(VISC) * NODES];
+    __shared__ double s_buf[tile_fields(VISC) * field_stride(NODES)];
     __shared__ double s_D[N2];
+    __shared__ double s_Dr[kRotRows<N> * N];
     __shared__ int s_face[2 * 6 * EPW];
     if (threadIdx.x < N2) s_D[threadIdx.x] = g.D[threadIdx.x];
+    if (threadIdx.x < kRotRows<N> * N) s_Dr[threadIdx.x] = rotated_D<N>(g.D, threadIdx.x);
     if constexpr (!PERSIST) {
         const long long vb = xcd_block(blockIdx.x, gridDim.x);
         const int b = find_problem(g.block_start, g.n, vb);
         const ResArgs a = problem_view(g, g.probs[b], g.out);
-        residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D, s_face);
+        residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D, s_Dr,
+                                                  s_face);
     } else {
         for (long long it = blockIdx.x; it < g.total_blocks; it += gridDim.x) {
             const long long vb = xcd_block(it, g.total_blocks);
             const int b = find_problem(g.block_start, g.n, vb);
             const ResArgs a = problem_view(g, g.probs[b], g.out);
-            residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D, s_face);
+            residual_tile<N, EPW, VISC, FLUX, MD, OR>(a, (vb - g.block_start[b]) * EPW, s_buf, s_D, s_Dr,
+                                                  s_face);
             __syncthreads();
         }
     }
