@@ -161,6 +161,12 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
     } else {
         int round = 0;
         const double igm1 = 1.0 / gm1;
+        // With two metric areas, the next direction's row goes into the other area during the last
+        // full round of the current direction and is published by that round's barrier.  The other
+        // area was last read by the previous direction, whose reads all precede a barrier of the
+        // current direction unless a half-round (even N) follows its last barrier and the current
+        // direction has only one full round; those cases stage after the rounds, with a barrier.
+        constexpr bool EARLY = !COMPACT && (N % 2 == 1 ? N >= 3 : N >= 6);
     #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int fa = (l & 1) ? F_A1 : F_A0;
@@ -168,12 +174,14 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                 // one metric area: the last half-round of the previous direction still reads it
                 if (l > 0) __syncthreads();
             }
-            if (tid < NODES) {
-                s_buf[(fa + 0) * FS + tid] = A[l][0];
-                s_buf[(fa + 1) * FS + tid] = A[l][1];
-                s_buf[(fa + 2) * FS + tid] = A[l][2];
+            if (!EARLY || l == 0) {
+                if (tid < NODES) {
+                    s_buf[(fa + 0) * FS + tid] = A[l][0];
+                    s_buf[(fa + 1) * FS + tid] = A[l][1];
+                    s_buf[(fa + 2) * FS + tid] = A[l][2];
+                }
+                __syncthreads();
             }
-            __syncthreads();
             const int il = idx[l];
             const int st = stride[l];
             auto pair = [&](int b, double f[5]) {
@@ -209,6 +217,14 @@ __device__ __forceinline__ void residual_tile(const ResArgs &a, long long ebase,
                     for (int c = 0; c < 5; ++c) {
                         acc[c] = fma(-dab, f[c], acc[c]);
                         s_buf[(fm + c) * FS + pn] = f[c];
+                    }
+                    if constexpr (EARLY) {
+                        if (l < 2 && 2 * (r + 1) >= N) {  // last full round: stage the next row
+                            const int fn = ((l + 1) & 1) ? F_A1 : F_A0;
+                            s_buf[(fn + 0) * FS + tid] = A[l + 1][0];
+                            s_buf[(fn + 1) * FS + tid] = A[l + 1][1];
+                            s_buf[(fn + 2) * FS + tid] = A[l + 1][2];
+                        }
                     }
                 }
                 __syncthreads();
