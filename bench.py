@@ -73,16 +73,12 @@ def trace_bytes(p, K, viscous):
 #             factors are those counters' readings for a plain 512 MiB device copy);
 #   trace_ms: average duration from --kernel-trace --stats;
 #   hw_flops: hardware FP64 operations per launch, (ADD + MUL + 2 FMA + TRANS) F64 x 64 lanes.
-# rocprofv3 figures of k_residual per schedule on the Taylor-Green workload (profiles/
-# k_residual_ns_tgv_p4_e32.md): HBM bytes per dispatch (FETCH_SIZE x 2 + WRITE_SIZE, scaled by a
-# plain device copy), trace-average duration, and hardware FP64 operations (ADD + MUL + 2 FMA +
-# TRANS wave instructions x 64 lanes).  Valid only for the kernel sources whose hash is given.
 KERNEL_PROFILE = {
-    "sha256": "68413c3a5850f1775df2db4fd9bed40f88a453bf6c932de64eb20dc97bbec3aa",
+    "sha256": "07cc4c09914efe8e4fba15a57dcbc949f35359ac64a3cdf87ab237ab54b1568d",
     "workload": "ns_tgv_p4_e32",
-    "bytes": {0: 1298908344, 1: 1294333160, 2: 1314481560, 3: 1241951224, 4: 1299503624,
-              5: 1296751400, 6: 1260826880},
-    "trace_ms": {0: 0.4193, 1: 0.4818, 2: 0.5556, 3: 0.5467, 4: 0.4341, 5: 0.4291, 6: 0.4095},
+    "bytes": {0: 1297725400, 1: 1291463624, 2: 1319203480, 3: 1238697688, 4: 1297378928,
+              5: 1295309520, 6: 1258448944},
+    "trace_ms": {0: 0.4249, 1: 0.4953, 2: 0.5811, 3: 0.5587, 4: 0.4349, 5: 0.4372, 6: 0.4275},
     "hw_flops": {0: 10234101760, 1: 10234101760, 2: 10221912064, 3: 10221912064, 4: 10234101760,
                  5: 10234101760, 6: 10234101760},
 }
