@@ -449,7 +449,7 @@ def tgv_robustness(P, W, dev, meshes, degrees, t_final, cfl, budget_s, chunk=100
 
             qs = [b[1].reshape(-1).clone() for b in built]
             ek0 = kinetic(qs[0])
-            alive = [0, 1, 2]
+            alive = list(range(len(schemes)))
             fail = {}
             t = 0.0
             steps = 0
